@@ -1,0 +1,262 @@
+"""Pins for the CPU oracle: it is checked against what the definitions and
+the mathematics fix, never against itself.
+
+* the 64-state table against the type definitions (prototype digraphs),
+  automorphism counts, relabelling invariance and an independent classifier;
+* the whole census against brute force (every triple) exhaustively on all
+  labelled digraphs with n <= 5, on random digraphs, and on R-MAT scale 10;
+* against networkx's triadic_census (an external library routine);
+* closed forms, linear counting identities and metamorphic relations;
+* against the wedge/triangle decomposition (a second exact algorithm).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_6308_amd import graphs
+
+from _helpers import (TYPES, arcs_of_code, check_identities, code_of, graph_quantities, permutations3,
+                      prototypes, random_digraph)
+
+
+def census_of(n, src, dst):
+    return oracle.census(graphs.build_csr(n, src, dst))
+
+
+# ---------------------------------------------------------------- the table
+
+def test_lut_prototypes():
+    lut = oracle.lut()
+    for t, arcs in prototypes().items():
+        # every labelling of the prototype (A,B,C) -> (u,v,w) lands on its class
+        for perm in permutations3():
+            c = code_of({(perm[a], perm[b]) for a, b in arcs})
+            assert TYPES[lut[c]] == t, (t, perm, c)
+
+
+def test_lut_class_sizes():
+    # labelled copies of a class = 3! / |automorphisms| (Sec. 3: 64 states, 16 classes)
+    expect = {"003": 1, "012": 6, "102": 3, "021D": 3, "021U": 3, "021C": 6, "111D": 6, "111U": 6,
+              "030T": 6, "030C": 2, "201": 3, "120D": 3, "120U": 3, "120C": 6, "210": 6, "300": 1}
+    lut = oracle.lut()
+    counts = {t: 0 for t in TYPES}
+    for c in range(64):
+        counts[TYPES[lut[c]]] += 1
+    assert counts == expect
+    assert sum(expect.values()) == 64
+
+
+def test_lut_relabel_invariant():
+    lut = oracle.lut()
+    for c in range(64):
+        arcs = arcs_of_code(c)
+        for perm in permutations3():
+            c2 = code_of({(perm[a], perm[b]) for a, b in arcs})
+            assert lut[c2] == lut[c]
+
+
+def test_two_classifiers_agree():
+    # brute force classifies by (M, A, sorted in/out degrees); the sweep's table
+    # by roles; they must agree on all 64 states
+    lut = oracle.lut()
+    for c in range(64):
+        sab = (c & 1) | ((c >> 1) & 1) << 1
+        sac = ((c >> 2) & 1) | ((c >> 3) & 1) << 1
+        sbc = ((c >> 4) & 1) | ((c >> 5) & 1) << 1
+        assert oracle.brute_classify(sab, sac, sbc) == lut[c]
+
+
+# ------------------------------------------------------- whole-census pins
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_exhaustive_small(n):
+    total, bad_sweep, bad_wedge = oracle.exhaustive(n)
+    assert total == 2 ** (n * (n - 1))
+    assert bad_sweep == 0 and bad_wedge == 0
+
+
+@pytest.mark.parametrize("n", [6, 13, 24, 40])
+@pytest.mark.parametrize("density", [0.05, 0.15, 0.4, 0.9])
+@pytest.mark.parametrize("recip", [0.0, 0.3, 1.0])
+def test_random_vs_brute(n, density, recip):
+    seed = n * 1000 + int(density * 100) * 10 + int(recip * 10)
+    s, d = random_digraph(n, density, recip, seed)
+    g = graphs.build_csr(n, s, d)
+    a = oracle.census(g)
+    assert a == oracle.brute(n, s, d)
+    assert a == oracle.wedge_census(g, 1)
+    check_identities(n, a, graph_quantities(n, s, d))
+
+
+def test_rmat10_vs_brute_and_identities():
+    g = graphs.workload("rmat10")
+    s, d = g.arcs()
+    a = oracle.census(g)
+    assert a == oracle.brute(g.n, s, d)  # 178,433,024 triples
+    assert a == oracle.wedge_census(g)
+    check_identities(g.n, a, graph_quantities(g.n, s, d))
+
+
+def test_networkx_triadic_census():
+    nx = pytest.importorskip("networkx")
+    cases = [graphs.workload("rmat10")]
+    for seed in range(3):
+        s, d = random_digraph(30, 0.3, 0.3, 77 + seed)
+        cases.append(graphs.build_csr(30, s, d))
+    for g in cases:
+        s, d = g.arcs()
+        G = nx.DiGraph()
+        G.add_nodes_from(range(g.n))
+        G.add_edges_from(zip(s.tolist(), d.tolist()))
+        ref = nx.triadic_census(G)
+        assert oracle.census(g) == [ref[t] for t in TYPES]
+
+
+# ------------------------------------------------------------ closed forms
+
+def only(n, **kw):
+    c = [0] * 16
+    for t, v in kw.items():
+        c[TYPES.index(t.replace("t", ""))] = v
+    c[0] = math.comb(n, 3) - sum(c[1:])
+    return c
+
+
+@pytest.mark.parametrize("n", [3, 4, 9, 17])
+def test_complete_digraph(n):
+    arcs = [(a, b) for a in range(n) for b in range(n) if a != b]
+    s, d = np.array(arcs).T
+    assert census_of(n, s, d) == only(n, t300=math.comb(n, 3))
+
+
+@pytest.mark.parametrize("n", [3, 5, 10])
+def test_transitive_tournament(n):
+    arcs = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    s, d = np.array(arcs).T
+    assert census_of(n, s, d) == only(n, t030T=math.comb(n, 3))
+
+
+@pytest.mark.parametrize("n", [4, 5, 12])
+def test_directed_cycle(n):
+    s = np.arange(n)
+    d = (s + 1) % n
+    assert census_of(n, s, d) == only(n, t021C=n, t012=n * (n - 4))
+
+
+def test_three_cycle():
+    assert census_of(3, np.array([0, 1, 2]), np.array([1, 2, 0])) == only(3, t030C=1)
+
+
+@pytest.mark.parametrize("k", [2, 3, 7])
+def test_stars(k):
+    n = k + 1
+    leaves = np.arange(1, n)
+    centre = np.zeros(k, dtype=int)
+    assert census_of(n, centre, leaves) == only(n, t021D=math.comb(k, 2))
+    assert census_of(n, leaves, centre) == only(n, t021U=math.comb(k, 2))
+    s = np.concatenate([centre, leaves])
+    d = np.concatenate([leaves, centre])
+    assert census_of(n, s, d) == only(n, t201=math.comb(k, 2))
+
+
+@pytest.mark.parametrize("n", [3, 6, 20])
+def test_single_dyads_and_empty(n):
+    assert census_of(n, np.array([0]), np.array([1])) == only(n, t012=n - 2)
+    assert census_of(n, np.array([0, 1]), np.array([1, 0])) == only(n, t102=n - 2)
+    assert census_of(n, np.array([], dtype=int), np.array([], dtype=int)) == only(n)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_fewer_than_three_vertices(n):
+    arcs = [(a, b) for a in range(n) for b in range(n) if a != b]
+    s = np.array([a for a, _ in arcs], dtype=np.int32)
+    d = np.array([b for _, b in arcs], dtype=np.int32)
+    assert census_of(n, s, d) == [0] * 16
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_mutual_only_graph(seed):
+    # from an undirected graph with m edges, T triangles and degrees d:
+    # 300 = T, 201 = sum C(d,2) - 3T, 102 = m(n-2) - 2*201 - 3*300
+    n = 25
+    s, d = random_digraph(n, 0.3, 1.0, seed)
+    q = graph_quantities(n, s, d)
+    m = q["M"]
+    c = census_of(n, s, d)
+    t300, t201 = q["T"], q["wedges"] - 3 * q["T"]
+    expect = only(n, t300=t300, t201=t201, t102=m * (n - 2) - 2 * t201 - 3 * t300)
+    assert c == expect
+
+
+# ------------------------------------------------------------ metamorphic
+
+def test_relabel_invariance():
+    n = 40
+    s, d = random_digraph(n, 0.2, 0.3, 5)
+    base = census_of(n, s, d)
+    rng = np.random.default_rng(9)
+    for _ in range(4):
+        p = rng.permutation(n)
+        assert census_of(n, p[s], p[d]) == base
+
+
+def test_reversal_swaps_d_and_u():
+    n = 40
+    s, d = random_digraph(n, 0.25, 0.2, 6)
+    a = dict(zip(TYPES, census_of(n, s, d)))
+    b = dict(zip(TYPES, census_of(n, d, s)))
+    swap = {"021D": "021U", "021U": "021D", "111D": "111U", "111U": "111D", "120D": "120U", "120U": "120D"}
+    for t in TYPES:
+        assert b[swap.get(t, t)] == a[t]
+
+
+def test_isolated_padding():
+    n, k = 30, 7
+    s, d = random_digraph(n, 0.3, 0.3, 7)
+    q = graph_quantities(n, s, d)
+    a = census_of(n, s, d)
+    b = census_of(n + k, s, d)
+    assert b[1] == a[1] + k * q["A"]
+    assert b[2] == a[2] + k * q["M"]
+    assert b[3:] == a[3:]
+    assert sum(b) == math.comb(n + k, 3)
+
+
+def test_disjoint_union_additive():
+    s1, d1 = random_digraph(20, 0.3, 0.3, 8)
+    s2, d2 = random_digraph(15, 0.4, 0.1, 9)
+    a = census_of(20, s1, d1)
+    b = census_of(15, s2, d2)
+    u = census_of(35, np.concatenate([s1, s2 + 20]), np.concatenate([d1, d2 + 20]))
+    assert u[3:] == [x + y for x, y in zip(a[3:], b[3:])]
+
+
+# ------------------------------------------------------------ arithmetic
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 4, 1024, 2642246, 2642247, 4801280, 4801281, 1 << 22, 1 << 24,
+                               2 ** 31 - 1])
+def test_choose3_128bit(n):
+    assert oracle.choose3(n) == math.comb(n, 3)
+
+
+def test_partial_censuses_add_up():
+    g = graphs.rmat(12, 8, seed=3)
+    full = oracle.census(g)
+    nb = g.nbrs.astype(np.int64)
+    rows = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    tasks = np.nonzero(nb > rows)[0]
+    rng = np.random.default_rng(1)
+    part = rng.integers(0, 3, size=tasks.size)
+    acc = np.zeros(16, dtype=object)
+    for k in range(3):
+        acc += np.array(oracle.census_tasks(g, tasks[part == k]), dtype=object)
+    assert list(acc[1:]) == full[1:]
+    assert oracle.census_tasks(g, tasks, nthreads=4)[1:] == full[1:]
+    assert oracle.census_mt(g, 3) == full
+
+
+def test_wedge_matches_sweep_rmat14():
+    g = graphs.rmat(14, 16, seed=4, recip_p=0.2)
+    assert oracle.wedge_census(g) == oracle.census_mt(g)
