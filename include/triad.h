@@ -1,0 +1,203 @@
+/*
+ * triad.h - C ABI of the MI355X directed triad census (libtriad.so).
+ *
+ * The census: for a simple digraph on vertices 0..n-1, the number of vertex
+ * triples in each of the 16 isomorphism classes, in the standard order
+ *     [0]=003 [1]=012 [2]=102 [3]=021D [4]=021U [5]=021C [6]=111D [7]=111U
+ *     [8]=030T [9]=030C [10]=201 [11]=120D [12]=120U [13]=120C [14]=210 [15]=300
+ * (Sec. 3 of Chin, Marquez, Choudhury, Feo, "Scalable Triadic Analysis of
+ * Large-Scale Graphs": 64 triad states condensed to 16 classes). 111D is
+ * A<->B<-C (the asymmetric arc points into the mutual dyad), 111U is A<->B->C.
+ *
+ * Method: the Batagelj-Mrvar edge sweep (Fig. 5 of the paper): for every
+ * symmetric edge {u,v} with u < v, the sorted neighbour lists N(u) and N(v)
+ * are merged (Sec. 6, Fig. 8); each third vertex w is classified from the
+ * direction bits of u-w and v-w (in situ, Sec. 6) when the triad is owned by
+ * this edge (v < w, or u < w < v with w not adjacent to u); the edge adds
+ * n - |N(u) u N(v)| triads to 012 (asymmetric u-v) or 102 (mutual u-v)
+ * (steps 2.1.2-2.1.3); 003 = C(n,3) minus the rest (steps 3-5). All counts
+ * are exact integers; the kernels are hand-written HIP for gfx950.
+ *
+ * Input graph (compact CSR of Sec. 6 / Fig. 7, direction bits kept in a
+ * separate packed array):
+ *   csr_offsets int64[n+1]   row x owns entries [csr_offsets[x], csr_offsets[x+1]);
+ *                            csr_offsets[0] = 0, non-decreasing, csr_offsets[n] = nnz
+ *   csr_nbrs    int32[nnz]   neighbour ids in [0,n), strictly increasing within a
+ *                            row, no self-loops; symmetric: y in N(x) iff x in N(y)
+ *   dir_flags   uint8[ceil(nnz/4)]  2 bits per entry, entry j at bits 2*(j&3) of
+ *                            byte j>>2: bit0 = arc row->neighbour, bit1 = arc
+ *                            neighbour->row; never 0; mirrored between (x,y) and (y,x)
+ * Limits: 0 <= n < 2^30, every degree < 2^31, nnz < 2^40.
+ *
+ * Output: out_u64[0..15] in the order above. Counts [1..15] are exact. 003 can
+ * exceed 2^64 (from n = 4,801,281): out_u64[0] then holds 003 mod 2^64, the
+ * status is TRIAD_OK_003_WRAPPED and the high word is returned where the entry
+ * point offers it. For n < 3 every count is 0.
+ *
+ * Ownership: inputs are borrowed read-only for the duration of the call and
+ * never retained or freed. On any error status (< 0) nothing is written to the
+ * outputs and triad_last_error() describes the cause (thread-local string).
+ * Calls are reentrant; calls on one stream run in stream order.
+ */
+#ifndef TRIAD_H
+#define TRIAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRIAD_ABI_VERSION 1
+
+enum triad_status {
+  TRIAD_OK = 0,
+  TRIAD_OK_003_WRAPPED = 1, /* success; 003 >= 2^64 (see above) */
+  TRIAD_EINVAL = -1,        /* null pointer, negative or too-large size, bad option */
+  TRIAD_EUNSORTED = -2,     /* a row is not strictly increasing (includes duplicates) */
+  TRIAD_ESELFLOOP = -3,     /* a vertex lists itself */
+  TRIAD_EASYM = -4,         /* CSR not symmetric or flags not mirrored (full validation) */
+  TRIAD_ERANGE = -5,        /* neighbour id outside [0,n), offsets not monotone or not
+                               ending at nnz, or a flag equal to 0 */
+  TRIAD_ENOMEM = -6,        /* device or host allocation failed */
+  TRIAD_EDEVICE = -7        /* no usable HIP device, or a HIP runtime error */
+};
+
+enum triad_schedule {
+  TRIAD_SCHED_PLAIN = 0,     /* tasks in CSR order */
+  TRIAD_SCHED_HEURISTIC = 1, /* tasks binned and ordered longest-first by d(u)+d(v) */
+  TRIAD_SCHED_LEARNED = 2    /* tasks binned and ordered by the learned cost model */
+};
+
+/* Device time of each stage of one census call, in milliseconds (HIP events
+ * on the call's stream). */
+typedef struct triad_timing {
+  float prep_ms;     /* pack ids with direction bits + validation */
+  float tasks_ms;    /* task enumeration (scan) and scheduling */
+  float census_ms;   /* the merge/classify kernel */
+  float finalize_ms; /* reduction and the null count */
+  int64_t tasks;     /* number of (u,v) tasks, u < v = symmetric edges */
+  int64_t hub_tasks; /* tasks split across several wavefronts */
+  int64_t items;     /* work items after splitting */
+} triad_timing;
+
+/* Options (a zeroed struct gives the defaults). */
+typedef struct triad_opts {
+  int32_t schedule;        /* enum triad_schedule */
+  int32_t validate;        /* 0 = O(nnz) checks of ranges, flags, order and self-loops
+                              (default), 1 = also symmetry and flag mirroring */
+  int64_t hub_threshold;   /* tasks with d(u)+d(v) above this are split into chunks
+                              merged by different wavefronts; 0 = default, < 0 = never */
+  int64_t chunk;           /* merge entries per chunk of a split task; 0 = default */
+  const float *model;      /* TRIAD_SCHED_LEARNED: device pointer to the cost-model
+                              weights (TRIAD_MLP_PARAMS floats); NULL = heuristic */
+  uint32_t *task_cycles;   /* optional device buffer [tasks]: receives per-task
+                              wavefront cycle counts, indexed in CSR task order */
+  triad_timing *timing;    /* optional host output */
+  int32_t waves_per_group; /* wavefronts per workgroup (1, 2, 4 or 8); 0 = default */
+  int32_t grid_groups;     /* persistent grid size in workgroups; 0 = default */
+} triad_opts;
+
+/* Census of one graph given by HOST pointers (copied to the device; the call
+ * blocks until the result is on the host). Default options; the high word of
+ * 003 is not returned (use triad_census_ex). */
+int triad_census(int64_t n, const int64_t *csr_offsets, const int32_t *csr_nbrs, const uint8_t *dir_flags,
+                 uint64_t out_u64[16]);
+
+/* As triad_census, with options (may be NULL) and the high word of 003
+ * (out_003_hi may be NULL). */
+int triad_census_ex(int64_t n, const int64_t *csr_offsets, const int32_t *csr_nbrs, const uint8_t *dir_flags,
+                    const triad_opts *opts, uint64_t out_u64[16], uint64_t *out_003_hi);
+
+/* Census of one graph given by DEVICE pointers (e.g. torch tensors), enqueued
+ * on `hip_stream` (a hipStream_t; NULL = the null stream). nnz must equal
+ * csr_offsets[n]. Results go to d_out (device, 17 x uint64: the 16 counts,
+ * then the high word of 003) and, if h_out is not NULL, to h_out (host, 17 x
+ * uint64). The call waits for its own work on the stream before returning the
+ * status. Scratch memory is taken from the stream-ordered allocator. */
+int triad_census_device(int64_t n, int64_t nnz, const int64_t *csr_offsets, const int32_t *csr_nbrs,
+                        const uint8_t *dir_flags, const triad_opts *opts, void *hip_stream, uint64_t *d_out,
+                        uint64_t *h_out);
+
+/* Host-side validation of the input contract (no device needed). level 0 =
+ * cheap checks, 1 = also symmetry and mirrored flags. Returns TRIAD_OK or the
+ * error status the census would return. */
+int triad_validate_host(int64_t n, const int64_t *csr_offsets, const int32_t *csr_nbrs, const uint8_t *dir_flags,
+                        int32_t level);
+
+/* ---------------------------------------------------------------- batches
+ * G graphs in one concatenated CSR held in DEVICE memory: graph g owns rows
+ * [vbase[g], vbase[g+1]) of csr_offsets (global entry positions) and its
+ * neighbour ids are graph-local (0 .. vbase[g+1]-vbase[g]-1). Each graph must
+ * satisfy the single-graph contract and have fewer than 4,801,281 vertices.
+ * A plan owns the scratch memory and a captured hipGraph of the whole batched
+ * census (one persistent launch); launching it replays the graph on a stream.
+ * d_out receives G x 16 uint64 (graph-major). */
+typedef struct triad_batch_plan triad_batch_plan;
+
+int triad_batch_plan_create(int32_t G, int64_t nv, int64_t nnz, const int64_t *d_vbase,
+                            const int64_t *d_offsets, const int32_t *d_nbrs, const uint8_t *d_flags,
+                            uint64_t *d_out, const triad_opts *opts, void *hip_stream, triad_batch_plan **plan);
+int triad_batch_plan_launch(triad_batch_plan *plan, void *hip_stream);
+/* Waits for the last launch and reports any validation error it found. */
+int triad_batch_plan_status(triad_batch_plan *plan);
+void triad_batch_plan_destroy(triad_batch_plan *plan);
+
+/* One-shot batched census (plan, launch, wait, destroy). */
+int triad_census_batch(int32_t G, int64_t nv, int64_t nnz, const int64_t *d_vbase, const int64_t *d_offsets,
+                       const int32_t *d_nbrs, const uint8_t *d_flags, const triad_opts *opts, void *hip_stream,
+                       uint64_t *d_out);
+
+/* Autotuner for the batched census: times the candidate launch shapes on the
+ * given batch with HIP events and returns the fastest in *best (its
+ * waves_per_group, grid_groups, hub_threshold and chunk fields are set).
+ * If cache_path is not NULL the result is read from / appended to that JSON
+ * lines file, keyed by the device name and a signature of the batch. */
+int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t *d_vbase, const int64_t *d_offsets,
+                         const int32_t *d_nbrs, const uint8_t *d_flags, void *hip_stream,
+                         const char *cache_path, triad_opts *best);
+
+/* ------------------------------------------------------- learned schedule
+ * Cost model: an FP32 multilayer perceptron 6 -> 32 -> 32 -> 1 with ReLU
+ * hidden layers. Parameters, packed in this order: W1[32][6], b1[32],
+ * W2[32][32], b2[32], W3[32], b3 (1313 floats). Input features of a task
+ * (u,v): log2(1+x) of d(u), d(v), d(u)+d(v), min, max, and the number of
+ * entries of N(u) above v. Target: log2 of the task's measured cycles. */
+#define TRIAD_MLP_IN 6
+#define TRIAD_MLP_HIDDEN 32
+#define TRIAD_MLP_PARAMS (TRIAD_MLP_HIDDEN * TRIAD_MLP_IN + TRIAD_MLP_HIDDEN + \
+                          TRIAD_MLP_HIDDEN * TRIAD_MLP_HIDDEN + TRIAD_MLP_HIDDEN + TRIAD_MLP_HIDDEN + 1)
+
+/* Features of every task (CSR task order) into d_feat [tasks][6] (device). */
+int triad_task_features(int64_t n, int64_t nnz, const int64_t *csr_offsets, const int32_t *csr_nbrs,
+                        void *hip_stream, float *d_feat, int64_t *ntasks_out);
+
+/* Forward pass: d_y[m] = model(d_x[m][6]) (all device pointers). */
+int triad_mlp_forward(const float *d_w, const float *d_x, int64_t m, float *d_y, void *hip_stream);
+
+/* Mean-squared-error loss and its gradient over m samples: d_grad
+ * [TRIAD_MLP_PARAMS] = d/dw (1/m) sum (model(x)-t)^2, d_loss[1] = the loss. */
+int triad_mlp_loss_grad(const float *d_w, const float *d_x, const float *d_t, int64_t m, float *d_grad,
+                        float *d_loss, void *hip_stream);
+
+/* One Adam step (Kingma and Ba) on d_w with moments d_m, d_v (device,
+ * TRIAD_MLP_PARAMS each) at step number t >= 1. */
+int triad_mlp_adam(float *d_w, float *d_m, float *d_v, const float *d_grad, int32_t t, float lr,
+                   void *hip_stream);
+
+/* Trains the cost model on the GPU: minibatch Adam on (features, log2 cycles)
+ * pairs, all device pointers; d_w holds the initial weights on entry and the
+ * trained weights on return; d_loss_hist (may be NULL) receives the mean loss
+ * of each epoch. */
+int triad_mlp_train(float *d_w, const float *d_x, const float *d_t, int64_t m, int32_t epochs, int32_t batch,
+                    float lr, uint64_t seed, void *hip_stream, float *d_loss_hist);
+
+/* ------------------------------------------------------------------ misc */
+const char *triad_last_error(void);
+int triad_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIAD_H */

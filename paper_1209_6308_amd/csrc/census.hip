@@ -1,0 +1,800 @@
+// Directed triad census on CDNA4 (gfx950): kernels and the single-graph
+// pipeline behind triad_census_device().
+//
+// Pipeline (one HIP stream, no host synchronisation until the end):
+//   k_rows      per row u: offset checks, first entry > u (binary search on the
+//               sorted row), self-loop check, tasks(u) = entries above u
+//   k_entries   per entry: neighbour/flag checks, sortedness, and the packed
+//               word id << 2 | flag (the compact id+direction encoding of
+//               Sec. 6 / Fig. 7, built once on the device)
+//   scan        exclusive prefix of tasks(u): the collapsed (u,v) task space
+//               of Fig. 5 steps 2 and 2.1
+//   k_emit      task list in CSR order; tasks whose merge length d(u)+d(v)
+//               exceeds the hub threshold go to the hub list instead
+//   k_census    persistent wavefronts: hub chunks first, then tasks; each
+//               item merges a range of N(u) with a range of N(v)
+//   k_finalize  003 = C(n,3) - sum of the rest, in two 64-bit words
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "triad_internal.h"
+
+namespace triad {
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      return fail(TRIAD_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr uint32_t KEY_INF = 0xFFFFFFFFu;  // larger than any key (ids < 2^30 - 1)
+constexpr uint64_t HUB_BIT = 1ull << 63;   // task moved to the hub list
+
+__device__ __forceinline__ uint32_t key_of(uint32_t p) { return p | 3u; }
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ uint32_t bcast32(uint32_t x, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+__device__ __forceinline__ uint64_t bcast64(uint64_t x, int lane) {
+  uint32_t lo = bcast32((uint32_t)x, lane), hi = bcast32((uint32_t)(x >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// ------------------------------------------------------------------ checks
+
+// Per row: offsets monotone, first entry above u, self-loop, task count.
+__global__ void k_rows(int64_t n, int64_t nnz, const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                       uint32_t* __restrict__ ustart, int64_t* __restrict__ ntask, uint32_t* __restrict__ rowmark,
+                       uint32_t* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    int64_t b = off[u], e = off[u + 1];
+    if (u == 0 && b != 0) atomicOr(err, ERR_RANGE);
+    if (u == n - 1 && e != nnz) atomicOr(err, ERR_RANGE);
+    if (e < b || b < 0 || e > nnz || e - b >= ((int64_t)1 << 31)) {
+      atomicOr(err, ERR_RANGE);
+      ustart[u] = 0;
+      ntask[u] = 0;
+      continue;
+    }
+    // first position with nbr > u (rows are sorted; checked by k_entries)
+    int64_t lo = b, hi = e;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if (nbr[mid] <= (int32_t)u) lo = mid + 1; else hi = mid;
+    }
+    if (lo > b && nbr[lo - 1] == (int32_t)u) atomicOr(err, ERR_SELFLOOP);
+    ustart[u] = (uint32_t)(lo - b);
+    ntask[u] = e - lo;
+    if (e > b) atomicOr(&rowmark[b >> 5], 1u << (b & 31));
+  }
+}
+
+// Per entry: id range, non-zero flag, strictly increasing rows; packed words.
+__global__ void k_entries(int64_t n, int64_t nnz, const int32_t* __restrict__ nbr, const uint8_t* __restrict__ flg,
+                          const uint32_t* __restrict__ rowmark, uint32_t* __restrict__ packed,
+                          uint32_t* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t bits = 0;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz; j += stride) {
+    int32_t y = nbr[j];
+    uint32_t f = (flg[j >> 2] >> (2 * (j & 3))) & 3u;
+    if (y < 0 || y >= n || f == 0) bits |= ERR_RANGE;
+    if (j + 1 < nnz) {
+      bool row_start = (rowmark[(j + 1) >> 5] >> ((j + 1) & 31)) & 1u;
+      if (!row_start && nbr[j + 1] <= y) bits |= ERR_UNSORTED;
+    }
+    packed[j] = ((uint32_t)y << 2) | f;
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+// Full validation: every entry has its mirror with swapped direction bits.
+__global__ void k_symmetry(int64_t n, const int64_t* __restrict__ off, const uint32_t* __restrict__ packed,
+                           const uint32_t* __restrict__ err_in, uint32_t* __restrict__ err) {
+  if (*err_in) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+    for (int64_t j = off[x]; j < off[x + 1]; ++j) {
+      uint32_t p = packed[j];
+      uint32_t y = p >> 2, f = p & 3u;
+      int64_t lo = off[y], hi = off[y + 1];
+      uint32_t want = ((uint32_t)x << 2) | 3u;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (key_of(packed[mid]) < want) lo = mid + 1; else hi = mid;
+      }
+      uint32_t g = ((f & 1u) << 1) | (f >> 1);
+      if (lo >= off[y + 1] || packed[lo] != (((uint32_t)x << 2) | g)) {
+        atomicOr(err, ERR_ASYM);
+        return;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------- exclusive scan
+// out[0..m] = exclusive prefix of in[0..m) (out[m] = total). Three passes:
+// block sums, a single-block scan of the block sums, block-local scans.
+constexpr int SCAN_T = 256, SCAN_I = 16, SCAN_B = SCAN_T * SCAN_I;
+
+__device__ int64_t block_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
+  // sh: SCAN_T/64 + 1 slots
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int k = 0; k < SCAN_T / 64; ++k) {
+      int64_t t = sh[k];
+      sh[k] = run;
+      run += t;
+    }
+    sh[SCAN_T / 64] = run;
+  }
+  __syncthreads();
+  int64_t r = x - v + sh[w];
+  *total = sh[SCAN_T / 64];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_scan_sums(const int64_t* __restrict__ in, int64_t m, int64_t* __restrict__ bsum) {
+  __shared__ int64_t sh[SCAN_T / 64 + 1];
+  int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I, s = 0;
+  for (int k = 0; k < SCAN_I; ++k)
+    if (base + k < m) s += in[base + k];
+  int64_t tot;
+  block_excl_scan(s, sh, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(int64_t* __restrict__ bsum, int64_t nb) {
+  __shared__ int64_t sh[SCAN_T / 64 + 1];
+  int64_t carry = 0;
+  for (int64_t c = 0; c < nb; c += SCAN_B) {
+    int64_t base = c + (int64_t)threadIdx.x * SCAN_I, loc[SCAN_I], s = 0;
+    for (int k = 0; k < SCAN_I; ++k) {
+      loc[k] = (base + k < nb) ? bsum[base + k] : 0;
+      s += loc[k];
+    }
+    int64_t tot, ex = block_excl_scan(s, sh, &tot);
+    int64_t run = carry + ex;
+    for (int k = 0; k < SCAN_I; ++k)
+      if (base + k < nb) { bsum[base + k] = run; run += loc[k]; }
+    carry += tot;
+  }
+}
+
+__global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t m, const int64_t* __restrict__ bsum,
+                             int64_t* __restrict__ out) {
+  __shared__ int64_t sh[SCAN_T / 64 + 1];
+  int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_I, loc[SCAN_I], s = 0;
+  for (int k = 0; k < SCAN_I; ++k) {
+    loc[k] = (base + k < m) ? in[base + k] : 0;
+    s += loc[k];
+  }
+  int64_t tot, run = block_excl_scan(s, sh, &tot) + bsum[blockIdx.x];
+  for (int k = 0; k < SCAN_I; ++k)
+    if (base + k < m) { out[base + k] = run; run += loc[k]; }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_T - 1) out[m] = run;
+}
+
+// --------------------------------------------------------------- task list
+// One wavefront per row: tasks of row u are its entries above u, written in
+// CSR order as (u << 32 | local index). Tasks longer than the hub threshold
+// are flagged and appended to the hub list with their chunk counts.
+__global__ void k_emit(int64_t n, const int64_t* __restrict__ off, const uint32_t* __restrict__ packed,
+                       const uint32_t* __restrict__ ustart, const int64_t* __restrict__ tpre,
+                       uint64_t* __restrict__ tasks, int64_t hub_threshold, int64_t chunk,
+                       uint64_t* __restrict__ hub_task, int64_t* __restrict__ hub_nch,
+                       unsigned long long* __restrict__ hub_count, const uint32_t* __restrict__ err) {
+  if (*err) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t u = wave; u < n; u += nwave) {
+    const int64_t b = off[u];
+    const int64_t du = off[u + 1] - b;
+    const uint32_t s = ustart[u];
+    const int64_t t0 = tpre[u];
+    const int64_t cnt = du - s;
+    for (int64_t i = lane; i < cnt; i += 64) {
+      uint32_t k = s + (uint32_t)i;
+      uint64_t tk = ((uint64_t)u << 32) | k;
+      if (hub_threshold >= 0) {
+        uint32_t v = packed[b + k] >> 2;
+        int64_t L = du + (off[v + 1] - off[v]);
+        if (L > hub_threshold) {
+          unsigned long long h = atomicAdd(hub_count, 1ull);
+          hub_task[h] = (uint64_t)(t0 + i);
+          hub_nch[h] = (L + chunk - 1) / chunk;
+          tk |= HUB_BIT;
+        }
+      }
+      tasks[t0 + i] = tk;
+    }
+  }
+}
+
+// ------------------------------------------------------------ the census
+
+struct CensusArgs {
+  int64_t n;
+  const int64_t* off;
+  const uint32_t* packed;
+  const uint64_t* tasks;
+  const int64_t* order;  // optional permutation of task indices (schedules)
+  int64_t ntasks;
+  const uint64_t* hub_task;
+  const int64_t* hub_pre;  // [nhub+1] exclusive prefix of chunk counts
+  int64_t nhub;
+  int64_t chunk;
+  unsigned long long* qctr;  // [2]: hub items, tasks
+  unsigned long long* acc;   // [16]
+  uint32_t* cycles;          // optional per-task cycles
+  const uint32_t* err;
+  ClassSlices cls;
+};
+
+constexpr int WIN = 512;  // entries per list per LDS window
+constexpr int BATCH = 64; // work items claimed per queue access
+
+struct WaveLds {
+  uint32_t a[WIN];
+  uint32_t b[WIN];
+  uint32_t hist[16 * 64];  // per-lane class counters [class][lane]
+};
+
+// Number of keys in s[0..m) that are <= bound (s sorted by key).
+__device__ __forceinline__ uint32_t upper_count(const uint32_t* s, uint32_t m, uint32_t bound) {
+  uint32_t lo = 0, hi = m;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (key_of(s[mid]) <= bound) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Merge A[0..la) with B[0..lb) (global, packed words, both sorted) across the
+// 64 lanes of one wavefront, classifying each distinct w. Equal ids of A and
+// B form one w (counted in `inter`). Windows of WIN entries per list are
+// staged in LDS; each round merges every element up to the smaller of the two
+// window maxima, so an id and its twin are always in the same round.
+__device__ __forceinline__ void merge_range(const uint32_t* __restrict__ A, uint32_t la,
+                                            const uint32_t* __restrict__ B, uint32_t lb, uint32_t uq, uint32_t vq,
+                                            uint64_t slice, WaveLds& L, int lane, uint64_t& inter) {
+  uint32_t ia = 0, ib = 0;
+  while (ia < la || ib < lb) {
+    const uint32_t ra = la - ia, rb = lb - ib;
+    const uint32_t na_ld = ra < WIN ? ra : WIN, nb_ld = rb < WIN ? rb : WIN;
+    for (uint32_t k = lane; k < WIN; k += 64) {
+      L.a[k] = k < na_ld ? A[ia + k] : KEY_INF;
+      L.b[k] = k < nb_ld ? B[ib + k] : KEY_INF;
+    }
+    wave_lds_sync();
+    const uint32_t lastA = na_ld < ra ? key_of(L.a[na_ld - 1]) : KEY_INF;
+    const uint32_t lastB = nb_ld < rb ? key_of(L.b[nb_ld - 1]) : KEY_INF;
+    uint32_t na, nb;
+    if (lastA <= lastB) {
+      na = na_ld;
+      nb = lastA == KEY_INF ? nb_ld : upper_count(L.b, nb_ld, lastA);
+    } else {
+      nb = nb_ld;
+      na = upper_count(L.a, na_ld, lastB);
+    }
+    const uint32_t D = na + nb;
+    const uint32_t d0 = (uint32_t)(((uint64_t)lane * D) >> 6), d1 = (uint32_t)(((uint64_t)(lane + 1) * D) >> 6);
+    // merge-path split at d0: i = number of A elements among the first d0
+    // (A goes first on equal ids)
+    uint32_t lo = d0 > nb ? d0 - nb : 0, hi = d0 < na ? d0 : na;
+    while (lo < hi) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (key_of(L.a[mid]) <= key_of(L.b[d0 - mid - 1])) lo = mid + 1; else hi = mid;
+    }
+    uint32_t i = lo, k = d0 - lo, pos = d0;
+    // an id shared by A[i-1] and B[k] was consumed with A[i-1] by the lane before
+    if (i > 0 && k < nb && key_of(L.a[i - 1]) == key_of(L.b[k])) { ++k; ++pos; }
+    uint32_t a = i < na ? L.a[i] : KEY_INF, b = k < nb ? L.b[k] : KEY_INF;
+    uint32_t both = 0;
+    while (pos < d1) {
+      const uint32_t ea = key_of(a), eb = key_of(b);
+      const bool tA = ea <= eb, tB = eb <= ea;
+      const uint32_t w = tA ? ea : eb;
+      const uint32_t fa = tA ? (a & 3u) : 0u, fb = tB ? (b & 3u) : 0u;
+      // canonical selection (Fig. 5 step 2.1.4): v < w, or u < w < v with w not in N(u)
+      if ((w > vq) | ((w > uq) & (fa == 0))) {
+        const uint32_t cls = (uint32_t)(slice >> ((fa | fb << 2) << 2)) & 15u;
+        atomicAdd(&L.hist[cls * 64 + lane], 1u);
+      }
+      both += (uint32_t)(tA & tB);
+      i += tA;
+      k += tB;
+      pos += (uint32_t)tA + (uint32_t)tB;
+      a = i < na ? L.a[i] : KEY_INF;
+      b = k < nb ? L.b[k] : KEY_INF;
+    }
+    inter += both;
+    wave_lds_sync();
+    ia += na;
+    ib += nb;
+  }
+}
+
+// Merge-path split of the diagonal d of A (la) and B (lb) in global memory:
+// the number of A elements among the first d merged (A first on equal ids).
+__device__ uint32_t global_split(const uint32_t* A, uint32_t la, const uint32_t* B, uint32_t lb, uint32_t d) {
+  uint32_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (key_of(A[mid]) <= key_of(B[d - mid - 1])) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ void flush_wave(WaveLds& L, int lane, unsigned long long* acc) {
+  for (int c = 3; c < 16; ++c) {
+    uint64_t s = wave_sum64(L.hist[c * 64 + lane]);
+    L.hist[c * 64 + lane] = 0;
+    if (lane == 0 && s) atomicAdd(&acc[c], (unsigned long long)s);
+  }
+  wave_lds_sync();
+}
+
+template <int WAVES>
+__global__ void __launch_bounds__(WAVES * 64) k_census(CensusArgs g) {
+  __shared__ WaveLds lds[WAVES];
+  if (*g.err) return;
+  const int lane = threadIdx.x & 63;
+  WaveLds& L = lds[threadIdx.x >> 6];
+  for (int c = 0; c < 16; ++c) L.hist[c * 64 + lane] = 0;
+  wave_lds_sync();
+  uint64_t inter_asym = 0, inter_mut = 0;  // per lane
+  uint64_t dy_asym = 0, dy_mut = 0;        // wave-uniform
+  uint64_t steps = 0;                      // bound on any lane's counter increments since the last flush
+
+  // ---- phase 1: chunks of hub tasks (merge-path partitions across wavefronts)
+  const int64_t hub_items = g.nhub ? g.hub_pre[g.nhub] : 0;
+  for (;;) {
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(&g.qctr[0], (unsigned long long)BATCH);
+    base = bcast64(base, 0);
+    if ((int64_t)base >= hub_items) break;
+    const int cnt = (int)min((int64_t)BATCH, hub_items - (int64_t)base);
+    // lane l resolves item base+l
+    int64_t aoff = 0, boff = 0;
+    uint32_t la = 0, lb = 0, u = 0, v = 0, f = 0, first = 0, dla = 0, dlb = 0;
+    if (lane < cnt) {
+      const int64_t item = (int64_t)base + lane;
+      int64_t lo = 0, hi = g.nhub;  // last h with hub_pre[h] <= item
+      while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (g.hub_pre[mid] <= item) lo = mid; else hi = mid;
+      }
+      const int64_t c = item - g.hub_pre[lo];
+      const uint64_t tk = g.tasks[g.hub_task[lo]] & ~HUB_BIT;
+      u = (uint32_t)(tk >> 32);
+      const int64_t au = g.off[u];
+      dla = (uint32_t)(g.off[u + 1] - au);
+      const uint32_t pv = g.packed[au + (uint32_t)tk];
+      v = pv >> 2;
+      f = pv & 3u;
+      const int64_t bv = g.off[v];
+      dlb = (uint32_t)(g.off[v + 1] - bv);
+      const uint32_t* Ag = g.packed + au;
+      const uint32_t* Bg = g.packed + bv;
+      const uint64_t Ltot = (uint64_t)dla + dlb;
+      const uint64_t d0 = (uint64_t)c * g.chunk, d1 = min(d0 + (uint64_t)g.chunk, Ltot);
+      uint32_t i0 = global_split(Ag, dla, Bg, dlb, (uint32_t)d0), k0 = (uint32_t)d0 - i0;
+      uint32_t i1 = global_split(Ag, dla, Bg, dlb, (uint32_t)d1), k1 = (uint32_t)d1 - i1;
+      if (i0 > 0 && k0 < dlb && key_of(Ag[i0 - 1]) == key_of(Bg[k0])) ++k0;
+      if (i1 > 0 && k1 < dlb && key_of(Ag[i1 - 1]) == key_of(Bg[k1])) ++k1;
+      if (k1 < k0) k1 = k0;
+      aoff = au + i0;
+      la = i1 - i0;
+      boff = bv + k0;
+      lb = k1 - k0;
+      first = c == 0;
+    }
+    for (int it = 0; it < cnt; ++it) {
+      const uint32_t su = bcast32(u, it), sv = bcast32(v, it), sf = bcast32(f, it);
+      const uint32_t sla = bcast32(la, it), slb = bcast32(lb, it);
+      const int64_t sao = (int64_t)bcast64((uint64_t)aoff, it), sbo = (int64_t)bcast64((uint64_t)boff, it);
+      uint64_t inter = 0;
+      merge_range(g.packed + sao, sla, g.packed + sbo, slb, (su << 2) | 3u, (sv << 2) | 3u, g.cls.s[sf], L, lane,
+                  inter);
+      if (sf == 3) inter_mut += inter; else inter_asym += inter;
+      if (bcast32(first, it)) {
+        const uint64_t dyad = (uint64_t)g.n - bcast32(dla, it) - bcast32(dlb, it);
+        if (sf == 3) dy_mut += dyad; else dy_asym += dyad;
+      }
+      steps += (sla + slb) / 64 + 2;
+      if (steps > (1ull << 30)) { flush_wave(L, lane, g.acc); steps = 0; }
+    }
+  }
+
+  // ---- phase 2: whole tasks (hub tasks are skipped here)
+  for (;;) {
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(&g.qctr[1], (unsigned long long)BATCH);
+    base = bcast64(base, 0);
+    if ((int64_t)base >= g.ntasks) break;
+    const int cnt = (int)min((int64_t)BATCH, g.ntasks - (int64_t)base);
+    int64_t aoff = 0, boff = 0, tid = 0;
+    uint32_t la = 0, lb = 0, u = 0, v = 0, f = 0, skip = 1;
+    if (lane < cnt) {
+      tid = g.order ? g.order[base + lane] : (int64_t)base + lane;
+      const uint64_t tk = g.tasks[tid];
+      skip = (tk & HUB_BIT) != 0;
+      u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
+      aoff = g.off[u];
+      la = (uint32_t)(g.off[u + 1] - aoff);
+      const uint32_t pv = g.packed[aoff + (uint32_t)tk];
+      v = pv >> 2;
+      f = pv & 3u;
+      boff = g.off[v];
+      lb = (uint32_t)(g.off[v + 1] - boff);
+    }
+    for (int it = 0; it < cnt; ++it) {
+      if (bcast32(skip, it)) continue;
+      const uint32_t su = bcast32(u, it), sv = bcast32(v, it), sf = bcast32(f, it);
+      const uint32_t sla = bcast32(la, it), slb = bcast32(lb, it);
+      const int64_t sao = (int64_t)bcast64((uint64_t)aoff, it), sbo = (int64_t)bcast64((uint64_t)boff, it);
+      uint64_t t_start = 0;
+      if (g.cycles) t_start = __builtin_amdgcn_s_memtime();
+      uint64_t inter = 0;
+      merge_range(g.packed + sao, sla, g.packed + sbo, slb, (su << 2) | 3u, (sv << 2) | 3u, g.cls.s[sf], L, lane,
+                  inter);
+      if (sf == 3) inter_mut += inter; else inter_asym += inter;
+      const uint64_t dyad = (uint64_t)g.n - sla - slb;
+      if (sf == 3) dy_mut += dyad; else dy_asym += dyad;
+      if (g.cycles) {
+        const uint64_t t_end = __builtin_amdgcn_s_memtime();
+        const int64_t st = (int64_t)bcast64((uint64_t)tid, it);
+        if (lane == 0) g.cycles[st] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
+      }
+      steps += (sla + slb) / 64 + 2;
+      if (steps > (1ull << 30)) { flush_wave(L, lane, g.acc); steps = 0; }
+    }
+  }
+  flush_wave(L, lane, g.acc);
+  const uint64_t ia = wave_sum64(inter_asym), im = wave_sum64(inter_mut);
+  if (lane == 0) {
+    atomicAdd(&g.acc[1], (unsigned long long)(dy_asym + ia));
+    atomicAdd(&g.acc[2], (unsigned long long)(dy_mut + im));
+  }
+}
+
+__global__ void k_finalize(const unsigned long long* __restrict__ acc, uint64_t clo, uint64_t chi,
+                           uint64_t* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t s = 0;
+  for (int c = 1; c < 16; ++c) {
+    out[c] = acc[c];
+    s += acc[c];
+  }
+  out[0] = clo - s;
+  out[16] = chi - (clo < s ? 1u : 0u);
+}
+
+__global__ void k_fill_u64(uint64_t* p, int64_t m, uint64_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, int64_t m, uint32_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) p[i] = v;
+}
+
+// ------------------------------------------------------------------- host
+
+static int grid_for(int64_t work, int threads, int cap = 65536) {
+  int64_t g = (work + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+// Stream-ordered scratch: freed on destruction in stream order.
+struct Scratch {
+  hipStream_t s;
+  std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t st) : s(st) {}
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+  template <class T>
+  hipError_t get(T** p, int64_t count) {
+    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMallocAsync((void**)p, bytes, s);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+};
+
+#define ALLOC(ptr, count)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = scratch.get(&(ptr), (count));                                                \
+    if (e_ != hipSuccess) {                                                                      \
+      (void)hipGetLastError();                                                                   \
+      return fail(TRIAD_ENOMEM, std::string("device allocation of ") + #ptr + " failed");       \
+    }                                                                                            \
+  } while (0)
+
+static int scan_excl(const int64_t* in, int64_t m, int64_t* out, Scratch& scratch, hipStream_t s) {
+  const int64_t nb = (m + SCAN_B - 1) / SCAN_B;
+  int64_t* bsum = nullptr;
+  ALLOC(bsum, nb + 1);
+  if (m > 0) {
+    k_scan_sums<<<(unsigned)nb, SCAN_T, 0, s>>>(in, m, bsum);
+    k_scan_top<<<1, SCAN_T, 0, s>>>(bsum, nb);
+    k_scan_apply<<<(unsigned)nb, SCAN_T, 0, s>>>(in, m, bsum, out);
+  } else {
+    k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)out, 1, 0);
+  }
+  HIPCHK(hipGetLastError());
+  return TRIAD_OK;
+}
+
+template <int WAVES>
+static void launch_census(const CensusArgs& a, int groups, hipStream_t s) {
+  k_census<WAVES><<<groups, WAVES * 64, 0, s>>>(a);
+}
+
+static int census_groups(int waves, int requested) {
+  if (requested > 0) return requested;
+  DeviceInfo di;
+  if (device_info(&di) != TRIAD_OK) return 1024;
+  int per_cu = 0;
+  hipError_t e;
+  switch (waves) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<1>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<2>, 128, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<8>, 512, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<4>, 256, 0); break;
+  }
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
+  return di.cus * per_cu;
+}
+
+struct Events {
+  hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool on = false;
+  ~Events() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  hipError_t init() {
+    on = true;
+    for (auto& x : e) {
+      hipError_t r = hipEventCreate(&x);
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  }
+  void rec(int i, hipStream_t s) {
+    if (on) (void)hipEventRecord(e[i], s);
+  }
+  float ms(int a, int b) {
+    float t = 0;
+    if (on) (void)hipEventElapsedTime(&t, e[a], e[b]);
+    return t;
+  }
+};
+
+int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
+                  const triad_opts* opts, hipStream_t s, uint64_t* d_out, uint64_t* h_out) {
+  triad_opts o{};
+  if (opts) o = *opts;
+  if (n < 0 || n >= ((int64_t)1 << 30)) return fail(TRIAD_EINVAL, "n must be in [0, 2^30)");
+  if (nnz < 0 || nnz >= ((int64_t)1 << 40)) return fail(TRIAD_EINVAL, "nnz must be in [0, 2^40)");
+  if (!off || !d_out || (nnz > 0 && (!nbr || !flg))) return fail(TRIAD_EINVAL, "NULL pointer argument");
+  if (o.validate < 0 || o.validate > 1) return fail(TRIAD_EINVAL, "validate must be 0 or 1");
+  if (o.schedule < 0 || o.schedule > 2) return fail(TRIAD_EINVAL, "unknown schedule");
+  int waves = o.waves_per_group ? o.waves_per_group : 4;
+  if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(TRIAD_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+  const int64_t chunk = o.chunk > 0 ? o.chunk : 32768;
+  const int64_t hub_thr = o.hub_threshold == 0 ? 65536 : o.hub_threshold;
+  if (chunk < 256 || chunk > ((int64_t)1 << 30)) return fail(TRIAD_EINVAL, "chunk must be in [256, 2^30]");
+  DeviceInfo di;
+  if (int st = device_info(&di)) return st;
+
+  Events ev;
+  if (o.timing) HIPCHK(ev.init());
+  Scratch scratch(s);
+  uint32_t* err = nullptr;
+  unsigned long long* acc = nullptr;  // [16] census accumulators + [2] queue counters + [1] hub count
+  ALLOC(err, 1);
+  ALLOC(acc, 19);
+  k_fill_u32<<<1, 64, 0, s>>>(err, 1, 0);
+  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)acc, 19, 0);
+  uint64_t clo, chi;
+  choose3(n, &clo, &chi);
+  ev.rec(0, s);
+  uint32_t *ustart = nullptr, *rowmark = nullptr, *packed = nullptr;
+  int64_t *ntask = nullptr, *tpre = nullptr;
+  if (n > 0) {
+    ALLOC(ustart, n);
+    ALLOC(ntask, n);
+    ALLOC(tpre, n + 1);
+    ALLOC(rowmark, (nnz >> 5) + 1);
+    ALLOC(packed, nnz);
+    k_fill_u32<<<grid_for((nnz >> 5) + 1, 256, 4096), 256, 0, s>>>(rowmark, (nnz >> 5) + 1, 0);
+    k_rows<<<grid_for(n, 256), 256, 0, s>>>(n, nnz, off, nbr, ustart, ntask, rowmark, err);
+    if (nnz > 0) {
+      k_entries<<<grid_for(nnz, 256, 16384), 256, 0, s>>>(n, nnz, nbr, flg, rowmark, packed, err);
+      if (o.validate == 1) k_symmetry<<<grid_for(n, 256), 256, 0, s>>>(n, off, packed, err, err);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  ev.rec(1, s);
+  // the task space and hub list need sizes on the host: read the task total
+  int64_t ntasks = 0, nhub = 0;
+  uint32_t errh = 0;
+  uint64_t* tasks = nullptr;
+  uint64_t* hub_task = nullptr;
+  int64_t *hub_nch = nullptr, *hub_pre = nullptr;
+  if (n > 0) {
+    if (int st = scan_excl(ntask, n, tpre, scratch, s)) return st;
+    HIPCHK(hipMemcpyAsync(&ntasks, tpre + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&errh, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (errh) {
+      int st = status_from_bits(errh);
+      return fail(st, st == TRIAD_ERANGE ? "neighbour id out of range, zero flag, or bad offsets"
+                      : st == TRIAD_ESELFLOOP ? "self-loop in the CSR"
+                      : st == TRIAD_EUNSORTED ? "row not strictly increasing"
+                                              : "CSR not symmetric or flags not mirrored");
+    }
+    if (ntasks * 2 != nnz) return fail(TRIAD_EASYM, "CSR is not symmetric (entries above and below the diagonal differ)");
+  }
+  if (ntasks > 0) {
+    ALLOC(tasks, ntasks);
+    const int64_t hub_cap = hub_thr >= 0 ? ntasks : 0;
+    ALLOC(hub_task, hub_cap);
+    ALLOC(hub_nch, hub_cap);
+    ALLOC(hub_pre, hub_cap + 1);
+    k_emit<<<grid_for(n * 64, 256, 32768), 256, 0, s>>>(n, off, packed, ustart, tpre, tasks, hub_thr, chunk, hub_task,
+                                                        hub_nch, acc + 18, err);
+    HIPCHK(hipGetLastError());
+    if (hub_thr >= 0) {
+      unsigned long long hc = 0;
+      HIPCHK(hipMemcpyAsync(&hc, acc + 18, sizeof(hc), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      nhub = (int64_t)hc;
+      if (nhub > 0) {
+        if (int st = scan_excl(hub_nch, nhub, hub_pre, scratch, s)) return st;
+      }
+    }
+  }
+  ev.rec(2, s);
+  if (ntasks > 0) {
+    CensusArgs a{};
+    a.n = n;
+    a.off = off;
+    a.packed = packed;
+    a.tasks = tasks;
+    a.order = nullptr;
+    a.ntasks = ntasks;
+    a.hub_task = hub_task;
+    a.hub_pre = hub_pre;
+    a.nhub = nhub;
+    a.chunk = chunk;
+    a.qctr = acc + 16;
+    a.acc = acc;
+    a.cycles = o.task_cycles;
+    a.err = err;
+    a.cls = class_slices();
+    const int groups = census_groups(waves, o.grid_groups);
+    switch (waves) {
+      case 1: launch_census<1>(a, groups, s); break;
+      case 2: launch_census<2>(a, groups, s); break;
+      case 8: launch_census<8>(a, groups, s); break;
+      default: launch_census<4>(a, groups, s); break;
+    }
+    HIPCHK(hipGetLastError());
+  }
+  ev.rec(3, s);
+  k_finalize<<<1, 64, 0, s>>>(acc, clo, chi, d_out);
+  HIPCHK(hipGetLastError());
+  ev.rec(4, s);
+  if (h_out) HIPCHK(hipMemcpyAsync(h_out, d_out, 17 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&errh, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (errh) return fail(status_from_bits(errh), "input validation failed on the device");
+  if (o.timing) {
+    o.timing->prep_ms = ev.ms(0, 1);
+    o.timing->tasks_ms = ev.ms(1, 2);
+    o.timing->census_ms = ev.ms(2, 3);
+    o.timing->finalize_ms = ev.ms(3, 4);
+    o.timing->tasks = ntasks;
+    o.timing->hub_tasks = nhub;
+    o.timing->items = ntasks;
+  }
+  return chi ? TRIAD_OK_003_WRAPPED : TRIAD_OK;
+}
+
+}  // namespace triad
+
+using namespace triad;
+
+extern "C" {
+
+int triad_census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
+                        const triad_opts* opts, void* stream, uint64_t* d_out, uint64_t* h_out) {
+  return census_device(n, nnz, off, nbr, flg, opts, (hipStream_t)stream, d_out, h_out);
+}
+
+int triad_census_ex(int64_t n, const int64_t* off, const int32_t* nbr, const uint8_t* flg, const triad_opts* opts,
+                    uint64_t out_u64[16], uint64_t* out_003_hi) {
+  if (!out_u64) return fail(TRIAD_EINVAL, "out_u64 is NULL");
+  int level = opts ? opts->validate : 0;
+  if (int st = triad_validate_host(n, off, nbr, flg, level)) return st;
+  const int64_t nnz = off[n];
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TRIAD_EDEVICE, "no HIP device available");
+  hipStream_t s;
+  HIPCHK(hipStreamCreate(&s));
+  int64_t* d_off = nullptr;
+  int32_t* d_nbr = nullptr;
+  uint8_t* d_flg = nullptr;
+  uint64_t* d_out = nullptr;
+  int st = TRIAD_OK;
+  auto cleanup = [&]() {
+    if (d_off) (void)hipFree(d_off);
+    if (d_nbr) (void)hipFree(d_nbr);
+    if (d_flg) (void)hipFree(d_flg);
+    if (d_out) (void)hipFree(d_out);
+    (void)hipStreamDestroy(s);
+  };
+  if (hipMalloc(&d_off, sizeof(int64_t) * (n + 1)) != hipSuccess ||
+      hipMalloc(&d_nbr, sizeof(int32_t) * std::max<int64_t>(nnz, 1)) != hipSuccess ||
+      hipMalloc(&d_flg, std::max<int64_t>((nnz + 3) / 4, 1)) != hipSuccess ||
+      hipMalloc(&d_out, 17 * sizeof(uint64_t)) != hipSuccess) {
+    cleanup();
+    return fail(TRIAD_ENOMEM, "device allocation for the input copy failed");
+  }
+  uint64_t h[17];
+  if (hipMemcpyAsync(d_off, off, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+      (nnz > 0 && hipMemcpyAsync(d_nbr, nbr, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s) != hipSuccess) ||
+      (nnz > 0 && hipMemcpyAsync(d_flg, flg, (nnz + 3) / 4, hipMemcpyHostToDevice, s) != hipSuccess)) {
+    cleanup();
+    return fail(TRIAD_EDEVICE, "host to device copy failed");
+  }
+  triad_opts o{};
+  if (opts) o = *opts;
+  o.validate = 0;  // checked on the host above
+  st = census_device(n, nnz, d_off, d_nbr, d_flg, &o, s, d_out, h);
+  if (st >= 0) {
+    std::memcpy(out_u64, h, 16 * sizeof(uint64_t));
+    if (out_003_hi) *out_003_hi = h[16];
+  }
+  cleanup();
+  return st;
+}
+
+int triad_census(int64_t n, const int64_t* off, const int32_t* nbr, const uint8_t* flg, uint64_t out_u64[16]) {
+  return triad_census_ex(n, off, nbr, flg, nullptr, out_u64, nullptr);
+}
+
+}  // extern "C"

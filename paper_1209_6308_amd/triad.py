@@ -1,0 +1,196 @@
+"""Python binding of ``libtriad.so`` (include/triad.h): argument marshalling only.
+
+Every step of the census runs in the library's HIP kernels. There is no CPU
+fallback: if the library is missing or no HIP device is present, the calls
+raise. PyTorch is used for device memory and streams only.
+
+Functions mirror the C entry points:
+
+* :func:`triad_census`         host arrays in, census out (blocking)
+* :func:`triad_census_device`  torch device tensors in, census out
+* :func:`triad_validate_host`  contract check on the host (no device needed)
+* batched plans, the autotuner and the learned-schedule entry points below
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import _build
+
+TYPES = ["003", "012", "102", "021D", "021U", "021C", "111D", "111U",
+         "030T", "030C", "201", "120D", "120U", "120C", "210", "300"]
+
+OK, OK_003_WRAPPED = 0, 1
+EINVAL, EUNSORTED, ESELFLOOP, EASYM, ERANGE, ENOMEM, EDEVICE = -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "TRIAD_OK", 1: "TRIAD_OK_003_WRAPPED", -1: "TRIAD_EINVAL", -2: "TRIAD_EUNSORTED",
+                -3: "TRIAD_ESELFLOOP", -4: "TRIAD_EASYM", -5: "TRIAD_ERANGE", -6: "TRIAD_ENOMEM",
+                -7: "TRIAD_EDEVICE"}
+SCHED = {"plain": 0, "heuristic": 1, "learned": 2}
+MLP_IN, MLP_HIDDEN = 6, 32
+MLP_PARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
+
+EXPORTS = [
+    "triad_census", "triad_census_ex", "triad_census_device", "triad_validate_host",
+    "triad_batch_plan_create", "triad_batch_plan_launch", "triad_batch_plan_status",
+    "triad_batch_plan_destroy", "triad_census_batch", "triad_batch_autotune",
+    "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
+    "triad_mlp_train", "triad_last_error", "triad_version",
+]
+
+
+class TriadError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("prep_ms", ctypes.c_float), ("tasks_ms", ctypes.c_float), ("census_ms", ctypes.c_float),
+                ("finalize_ms", ctypes.c_float), ("tasks", ctypes.c_int64), ("hub_tasks", ctypes.c_int64),
+                ("items", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("validate", ctypes.c_int32), ("hub_threshold", ctypes.c_int64),
+                ("chunk", ctypes.c_int64), ("model", ctypes.c_void_p), ("task_cycles", ctypes.c_void_p),
+                ("timing", ctypes.POINTER(Timing)), ("waves_per_group", ctypes.c_int32),
+                ("grid_groups", ctypes.c_int32)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libtriad.so (built by __graft_entry__.build()); raises if absent."""
+    global _LIB
+    if _LIB is None:
+        path = _build.triad_lib_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(path)
+        i64, i32, vp, u64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint64
+        po = ctypes.POINTER(Opts)
+        sigs = {
+            "triad_census": [i64, vp, vp, vp, vp],
+            "triad_census_ex": [i64, vp, vp, vp, po, vp, vp],
+            "triad_census_device": [i64, i64, vp, vp, vp, po, vp, vp, vp],
+            "triad_validate_host": [i64, vp, vp, vp, i32],
+            "triad_batch_plan_create": [i32, i64, i64, vp, vp, vp, vp, vp, po, vp, ctypes.POINTER(vp)],
+            "triad_batch_plan_launch": [vp, vp],
+            "triad_batch_plan_status": [vp],
+            "triad_batch_plan_destroy": [vp],
+            "triad_census_batch": [i32, i64, i64, vp, vp, vp, vp, po, vp, vp],
+            "triad_batch_autotune": [i32, i64, i64, vp, vp, vp, vp, vp, ctypes.c_char_p, po],
+            "triad_task_features": [i64, i64, vp, vp, vp, vp, ctypes.POINTER(i64)],
+            "triad_mlp_forward": [vp, vp, i64, vp, vp],
+            "triad_mlp_loss_grad": [vp, vp, vp, i64, vp, vp, vp],
+            "triad_mlp_adam": [vp, vp, vp, vp, i32, ctypes.c_float, vp],
+            "triad_mlp_train": [vp, vp, vp, i64, i32, i32, ctypes.c_float, u64, vp, vp],
+            "triad_last_error": [],
+            "triad_version": [],
+        }
+        for name, args in sigs.items():
+            if hasattr(L, name):
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = ctypes.c_int
+        L.triad_last_error.restype = ctypes.c_char_p
+        if hasattr(L, "triad_batch_plan_destroy"):
+            L.triad_batch_plan_destroy.restype = None
+        _LIB = L
+    return _LIB
+
+
+def last_error():
+    return lib().triad_last_error().decode()
+
+
+def _check(st):
+    if st < 0:
+        raise TriadError(st, last_error())
+    return st
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def _tp(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def make_opts(schedule="plain", validate=0, hub_threshold=0, chunk=0, model=None, task_cycles=None,
+              waves_per_group=0, grid_groups=0, timing=None):
+    o = Opts()
+    o.schedule = SCHED[schedule] if isinstance(schedule, str) else int(schedule)
+    o.validate = validate
+    o.hub_threshold = hub_threshold
+    o.chunk = chunk
+    o.model = model.data_ptr() if model is not None else None
+    o.task_cycles = task_cycles.data_ptr() if task_cycles is not None else None
+    o.waves_per_group = waves_per_group
+    o.grid_groups = grid_groups
+    if timing is not None:
+        o.timing = ctypes.pointer(timing)
+    return o
+
+
+def _result(out, hi):
+    res = [int(x) for x in out[:16]]
+    res[0] += int(hi) << 64
+    return res
+
+
+def triad_validate_host(n, offsets, nbrs, flags, level=0):
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    nb = np.ascontiguousarray(nbrs, dtype=np.int32)
+    fl = np.ascontiguousarray(flags, dtype=np.uint8)
+    return lib().triad_validate_host(n, _p(off), _p(nb), _p(fl), level)
+
+
+def triad_census(n, offsets, nbrs, flags, **kw):
+    """Census from host arrays; returns 16 Python ints (003 including its high word)."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    nb = np.ascontiguousarray(nbrs, dtype=np.int32)
+    fl = np.ascontiguousarray(flags, dtype=np.uint8)
+    out = np.zeros(16, dtype=np.uint64)
+    hi = np.zeros(1, dtype=np.uint64)
+    o = make_opts(**kw)
+    _check(lib().triad_census_ex(n, _p(off), _p(nb), _p(fl), ctypes.byref(o), _p(out), _p(hi)))
+    return _result(out, hi[0])
+
+
+def triad_census_device(n, nnz, d_off, d_nbr, d_flg, stream=None, d_out=None, **kw):
+    """Census from torch device tensors (int64 offsets, int32 ids, uint8 flags).
+
+    Returns (counts, status, timing dict). `d_out` (uint64/int64 tensor with 17
+    elements on the device) may be given to receive the raw output."""
+    import torch
+    if d_out is None:
+        d_out = torch.empty(17, dtype=torch.int64, device=d_off.device)
+    h = np.zeros(17, dtype=np.uint64)
+    tm = Timing()
+    o = make_opts(timing=tm, **kw)
+    st = _check(lib().triad_census_device(n, nnz, _tp(d_off), _tp(d_nbr), _tp(d_flg), ctypes.byref(o),
+                                          _stream(stream), _tp(d_out), _p(h)))
+    return _result(h, h[16]), st, tm.as_dict()
+
+
+def to_device(g, device="cuda"):
+    """Copy a CSR (graphs.CSR) to device tensors: (off, nbrs, flags)."""
+    import torch
+    return (torch.from_numpy(g.offsets).to(device), torch.from_numpy(g.nbrs).to(device),
+            torch.from_numpy(g.flags).to(device))

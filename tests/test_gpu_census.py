@@ -1,0 +1,166 @@
+"""GPU census through the C ABI, compared element by element with the CPU
+oracle (bit-exact: every count is an integer)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_6308_amd import graphs, triad
+
+from _helpers import GOLDEN, random_digraph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def gpu_census(g, **kw):
+    d = triad.to_device(g, "cuda")
+    got, st, tm = triad.triad_census_device(g.n, g.nnz, *d, **kw)
+    return got, st, tm
+
+
+@pytest.mark.parametrize("n,density,recip,seed", [
+    (3, 1.0, 1.0, 1), (4, 0.5, 0.3, 2), (10, 0.3, 0.0, 3), (25, 0.5, 0.5, 4), (40, 0.9, 0.3, 5),
+    (64, 0.2, 1.0, 6), (65, 0.15, 0.2, 7), (130, 0.1, 0.3, 8), (300, 0.05, 0.1, 9), (600, 0.6, 0.2, 10),
+])
+def test_random_small(torch_cuda, n, density, recip, seed):
+    s, d = random_digraph(n, density, recip, seed)
+    g = graphs.build_csr(n, s, d)
+    got, st, _ = gpu_census(g)
+    assert got == oracle.census(g)
+    assert st == 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 7])
+def test_degenerate(torch_cuda, n):
+    g = graphs.build_csr(n, np.array([], np.int32), np.array([], np.int32))
+    got, st, _ = gpu_census(g)
+    assert got == oracle.census(g)
+    if n >= 2:
+        g = graphs.from_arcs(n, [(0, 1)])
+        assert gpu_census(g)[0] == oracle.census(g)
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+@pytest.mark.parametrize("hub", [(-1, 0), (0, 0), (64, 256), (300, 1000)])
+def test_rmat_launch_shapes(torch_cuda, waves, hub):
+    # scale 12 spans many LDS windows (d_max ~ 800) and ragged tails
+    g = graphs.rmat(12, 8, seed=5, recip_p=0.15)
+    want = oracle.census(g)
+    got, st, tm = gpu_census(g, waves_per_group=waves, hub_threshold=hub[0], chunk=hub[1])
+    assert got == want
+    if hub[0] == 64:
+        assert tm["hub_tasks"] > 0
+
+
+def test_rmat10_and_grid_sizes(torch_cuda):
+    g = graphs.workload("rmat10")
+    want = oracle.census(g)
+    for groups in (1, 3, 64, 2048):
+        assert gpu_census(g, grid_groups=groups)[0] == want
+
+
+def test_hub_heavy_star_and_clique(torch_cuda):
+    # a vertex adjacent to all others, plus a dense core: long merges, many twins
+    n = 3000
+    s = [0] * (n - 1) + list(range(1, n))
+    d = list(range(1, n)) + [0] * 200 + [0] * (n - 1 - 200)
+    s = s[: n - 1] + list(range(1, 201))
+    d = d[: n - 1] + [0] * 200
+    core = [(a, b) for a in range(1, 60) for b in range(1, 60) if a != b and (a * 7 + b) % 3]
+    s += [a for a, _ in core]
+    d += [b for _, b in core]
+    g = graphs.build_csr(n, np.array(s), np.array(d))
+    want = oracle.census(g)
+    for thr, ch in ((-1, 0), (512, 256), (4000, 1024)):
+        assert gpu_census(g, hub_threshold=thr, chunk=ch)[0] == want
+
+
+def test_deterministic_repeats(torch_cuda):
+    g = graphs.rmat(14, 8, seed=2, recip_p=0.1)
+    want = oracle.census_mt(g)
+    for _ in range(3):
+        assert gpu_census(g)[0] == want
+
+
+def test_relabel_and_reverse_on_gpu(torch_cuda):
+    s, d = random_digraph(200, 0.1, 0.2, 11)
+    base = gpu_census(graphs.build_csr(200, s, d))[0]
+    p = np.random.default_rng(3).permutation(200)
+    assert gpu_census(graphs.build_csr(200, p[s], p[d]))[0] == base
+    rev = gpu_census(graphs.build_csr(200, d, s))[0]
+    sw = [0, 1, 2, 4, 3, 5, 7, 6, 8, 9, 10, 12, 11, 13, 14, 15]
+    assert [rev[sw[k]] for k in range(16)] == base
+
+
+def test_host_pointer_entry(torch_cuda):
+    g = graphs.rmat(11, 8, seed=7, recip_p=0.3)
+    assert triad.triad_census(g.n, g.offsets, g.nbrs, g.flags) == oracle.census(g)
+
+
+def _bad(kind):
+    g = graphs.rmat(8, 4, seed=1)
+    off, nb, fl = g.offsets.copy(), g.nbrs.copy(), g.flags.copy()
+    r = int(np.argmax(np.diff(off)))
+    b = int(off[r])
+    if kind == "unsorted":
+        nb[b], nb[b + 1] = nb[b + 1], nb[b]
+    elif kind == "selfloop":
+        nb[b] = r
+        nb[b:off[r + 1]].sort()
+    elif kind == "range":
+        nb[-1] = g.n + 5
+    elif kind == "flag0":
+        fl[0] &= 0xFC
+    return g.n, off, nb, fl
+
+
+@pytest.mark.parametrize("kind,status", [("unsorted", triad.EUNSORTED), ("selfloop", triad.ESELFLOOP),
+                                         ("range", triad.ERANGE), ("flag0", triad.ERANGE)])
+def test_device_validation_errors(torch_cuda, kind, status):
+    torch = torch_cuda
+    n, off, nb, fl = _bad(kind)
+    d = [torch.from_numpy(a).cuda() for a in (off, nb, fl)]
+    out = torch.full((17,), 7, dtype=torch.int64, device="cuda")
+    with pytest.raises(triad.TriadError) as e:
+        triad.triad_census_device(n, int(off[-1]), *d, d_out=out)
+    assert e.value.status == status
+    assert torch.all(out == 7), "output written on error"
+
+
+def test_device_symmetry_validation(torch_cuda):
+    torch = torch_cuda
+    g = graphs.rmat(8, 4, seed=1)
+    fl = g.flags.copy()
+    f0 = fl[0] & 3
+    fl[0] = (fl[0] & 0xFC) | (3 if f0 != 3 else 1)  # flag of entry 0 no longer mirrored
+    d = [torch.from_numpy(a).cuda() for a in (g.offsets, g.nbrs, fl)]
+    with pytest.raises(triad.TriadError) as e:
+        triad.triad_census_device(g.n, g.nnz, *d, validate=1)
+    assert e.value.status == triad.EASYM
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"census_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["rmat20"])
+def test_full_size_golden(torch_cuda, name):
+    rec = _golden(name)
+    g = graphs.workload(name)
+    assert g.content_hash() == rec["content_hash"]
+    got, st, tm = gpu_census(g)
+    assert [str(x) for x in got] == rec["census"]
