@@ -94,7 +94,7 @@ typedef struct triad_opts {
   uint32_t *task_cycles;   /* optional device buffer [tasks]: receives per-task
                               wavefront cycle counts, indexed in CSR task order */
   triad_timing *timing;    /* optional host output */
-  int32_t waves_per_group; /* wavefronts per workgroup (1, 2, 4 or 8); 0 = default */
+  int32_t waves_per_group; /* wavefronts per workgroup (1, 2 or 4); 0 = default */
   int32_t grid_groups;     /* persistent grid size in workgroups; 0 = default */
 } triad_opts;
 

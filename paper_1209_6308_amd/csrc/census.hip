@@ -254,92 +254,20 @@ struct CensusArgs {
   unsigned long long* acc;   // [16]
   uint32_t* cycles;          // optional per-task cycles
   const uint32_t* err;
-  ClassSlices cls;
+  ClassSlices cls;           // nibble idx = fa | fb << 2 -> class; idx 0 -> 0 (not counted)
 };
 
-constexpr int WIN = 512;  // entries per list per LDS window
-constexpr int BATCH = 64; // work items claimed per queue access
+constexpr int BATCH = 64;   // work items claimed per queue access
+constexpr int PAD = 1024;   // readable entries past the end of the packed array
 
+// Per-wavefront LDS: two sorted windows (plus a sentinel slot each) and
+// lane-private class counters.
+template <int W>
 struct WaveLds {
-  uint32_t a[WIN];
-  uint32_t b[WIN];
-  uint32_t hist[16 * 64];  // per-lane class counters [class][lane]
+  uint32_t a[W + 1];
+  uint32_t b[W + 1];
+  uint32_t hist[16 * 64];  // [class][lane]
 };
-
-// Number of keys in s[0..m) that are <= bound (s sorted by key).
-__device__ __forceinline__ uint32_t upper_count(const uint32_t* s, uint32_t m, uint32_t bound) {
-  uint32_t lo = 0, hi = m;
-  while (lo < hi) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (key_of(s[mid]) <= bound) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
-
-// Merge A[0..la) with B[0..lb) (global, packed words, both sorted) across the
-// 64 lanes of one wavefront, classifying each distinct w. Equal ids of A and
-// B form one w (counted in `inter`). Windows of WIN entries per list are
-// staged in LDS; each round merges every element up to the smaller of the two
-// window maxima, so an id and its twin are always in the same round.
-__device__ __forceinline__ void merge_range(const uint32_t* __restrict__ A, uint32_t la,
-                                            const uint32_t* __restrict__ B, uint32_t lb, uint32_t uq, uint32_t vq,
-                                            uint64_t slice, WaveLds& L, int lane, uint64_t& inter) {
-  uint32_t ia = 0, ib = 0;
-  while (ia < la || ib < lb) {
-    const uint32_t ra = la - ia, rb = lb - ib;
-    const uint32_t na_ld = ra < WIN ? ra : WIN, nb_ld = rb < WIN ? rb : WIN;
-    for (uint32_t k = lane; k < WIN; k += 64) {
-      L.a[k] = k < na_ld ? A[ia + k] : KEY_INF;
-      L.b[k] = k < nb_ld ? B[ib + k] : KEY_INF;
-    }
-    wave_lds_sync();
-    const uint32_t lastA = na_ld < ra ? key_of(L.a[na_ld - 1]) : KEY_INF;
-    const uint32_t lastB = nb_ld < rb ? key_of(L.b[nb_ld - 1]) : KEY_INF;
-    uint32_t na, nb;
-    if (lastA <= lastB) {
-      na = na_ld;
-      nb = lastA == KEY_INF ? nb_ld : upper_count(L.b, nb_ld, lastA);
-    } else {
-      nb = nb_ld;
-      na = upper_count(L.a, na_ld, lastB);
-    }
-    const uint32_t D = na + nb;
-    const uint32_t d0 = (uint32_t)(((uint64_t)lane * D) >> 6), d1 = (uint32_t)(((uint64_t)(lane + 1) * D) >> 6);
-    // merge-path split at d0: i = number of A elements among the first d0
-    // (A goes first on equal ids)
-    uint32_t lo = d0 > nb ? d0 - nb : 0, hi = d0 < na ? d0 : na;
-    while (lo < hi) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (key_of(L.a[mid]) <= key_of(L.b[d0 - mid - 1])) lo = mid + 1; else hi = mid;
-    }
-    uint32_t i = lo, k = d0 - lo, pos = d0;
-    // an id shared by A[i-1] and B[k] was consumed with A[i-1] by the lane before
-    if (i > 0 && k < nb && key_of(L.a[i - 1]) == key_of(L.b[k])) { ++k; ++pos; }
-    uint32_t a = i < na ? L.a[i] : KEY_INF, b = k < nb ? L.b[k] : KEY_INF;
-    uint32_t both = 0;
-    while (pos < d1) {
-      const uint32_t ea = key_of(a), eb = key_of(b);
-      const bool tA = ea <= eb, tB = eb <= ea;
-      const uint32_t w = tA ? ea : eb;
-      const uint32_t fa = tA ? (a & 3u) : 0u, fb = tB ? (b & 3u) : 0u;
-      // canonical selection (Fig. 5 step 2.1.4): v < w, or u < w < v with w not in N(u)
-      if ((w > vq) | ((w > uq) & (fa == 0))) {
-        const uint32_t cls = (uint32_t)(slice >> ((fa | fb << 2) << 2)) & 15u;
-        atomicAdd(&L.hist[cls * 64 + lane], 1u);
-      }
-      both += (uint32_t)(tA & tB);
-      i += tA;
-      k += tB;
-      pos += (uint32_t)tA + (uint32_t)tB;
-      a = i < na ? L.a[i] : KEY_INF;
-      b = k < nb ? L.b[k] : KEY_INF;
-    }
-    inter += both;
-    wave_lds_sync();
-    ia += na;
-    ib += nb;
-  }
-}
 
 // Merge-path split of the diagonal d of A (la) and B (lb) in global memory:
 // the number of A elements among the first d merged (A first on equal ids).
@@ -352,136 +280,299 @@ __device__ uint32_t global_split(const uint32_t* A, uint32_t la, const uint32_t*
   return lo;
 }
 
-__device__ void flush_wave(WaveLds& L, int lane, unsigned long long* acc) {
+// One batch of work items, one item per lane (lane < cnt). An item merges
+// A = packed[aoff .. aoff+la) (a range of N(u)) with B = packed[boff ..
+// boff+lb) (a range of N(v)); `first` items (1 = chunk 0 of a split task,
+// 2 = a whole task) also add the dyadic count of their task, whose full list
+// lengths are dla, dlb.
+struct Batch {
+  int cnt;
+  int64_t aoff, boff, tid;
+  uint32_t la, lb, u, v, f, first, dla, dlb;
+};
+
+// Claims the next batch: hub chunks first (phase 0), then whole tasks
+// (phase 1). Returns false when both queues are drained.
+__device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt) {
+  const int64_t hub_items = g.nhub ? g.hub_pre[g.nhub] : 0;
+  for (;;) {
+    if (phase == 0) {
+      uint64_t base = 0;
+      if (lane == 0) base = atomicAdd(&g.qctr[0], (unsigned long long)BATCH);
+      base = bcast64(base, 0);
+      if ((int64_t)base >= hub_items) { phase = 1; continue; }
+      bt.cnt = (int)min((int64_t)BATCH, hub_items - (int64_t)base);
+      bt.la = bt.lb = bt.u = bt.v = bt.f = bt.first = bt.dla = bt.dlb = 0;
+      bt.aoff = bt.boff = bt.tid = 0;
+      if (lane < bt.cnt) {
+        const int64_t item = (int64_t)base + lane;
+        int64_t lo = 0, hi = g.nhub;  // last h with hub_pre[h] <= item
+        while (hi - lo > 1) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (g.hub_pre[mid] <= item) lo = mid; else hi = mid;
+        }
+        const int64_t c = item - g.hub_pre[lo];
+        bt.tid = (int64_t)g.hub_task[lo];
+        const uint64_t tk = g.tasks[bt.tid] & ~HUB_BIT;
+        bt.u = (uint32_t)(tk >> 32);
+        const int64_t au = g.off[bt.u];
+        bt.dla = (uint32_t)(g.off[bt.u + 1] - au);
+        const uint32_t pv = g.packed[au + (uint32_t)tk];
+        bt.v = pv >> 2;
+        bt.f = pv & 3u;
+        const int64_t bv = g.off[bt.v];
+        bt.dlb = (uint32_t)(g.off[bt.v + 1] - bv);
+        const uint32_t* Ag = g.packed + au;
+        const uint32_t* Bg = g.packed + bv;
+        const uint64_t Ltot = (uint64_t)bt.dla + bt.dlb;
+        const uint64_t d0 = (uint64_t)c * g.chunk, d1 = min(d0 + (uint64_t)g.chunk, Ltot);
+        const uint32_t i0 = global_split(Ag, bt.dla, Bg, bt.dlb, (uint32_t)d0);
+        const uint32_t i1 = global_split(Ag, bt.dla, Bg, bt.dlb, (uint32_t)d1);
+        uint32_t k0 = (uint32_t)d0 - i0, k1 = (uint32_t)d1 - i1;
+        // an id shared by A and B stays with the chunk holding its A copy
+        if (i0 > 0 && k0 < bt.dlb && key_of(Ag[i0 - 1]) == key_of(Bg[k0])) ++k0;
+        if (i1 > 0 && k1 < bt.dlb && key_of(Ag[i1 - 1]) == key_of(Bg[k1])) ++k1;
+        if (k1 < k0) k1 = k0;
+        bt.aoff = au + i0;
+        bt.la = i1 - i0;
+        bt.boff = bv + k0;
+        bt.lb = k1 - k0;
+        bt.first = c == 0;
+      }
+      return true;
+    }
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(&g.qctr[1], (unsigned long long)BATCH);
+    base = bcast64(base, 0);
+    if ((int64_t)base >= g.ntasks) return false;
+    bt.cnt = (int)min((int64_t)BATCH, g.ntasks - (int64_t)base);
+    bt.la = bt.lb = bt.u = bt.v = bt.f = bt.first = bt.dla = bt.dlb = 0;
+    bt.aoff = bt.boff = bt.tid = 0;
+    if (lane < bt.cnt) {
+      bt.tid = g.order ? g.order[base + lane] : (int64_t)base + lane;
+      const uint64_t tk = g.tasks[bt.tid];
+      if (!(tk & HUB_BIT)) {  // hub tasks were merged in phase 0: empty item here
+        bt.u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
+        bt.aoff = g.off[bt.u];
+        bt.la = (uint32_t)(g.off[bt.u + 1] - bt.aoff);
+        const uint32_t pv = g.packed[bt.aoff + (uint32_t)tk];
+        bt.v = pv >> 2;
+        bt.f = pv & 3u;
+        bt.boff = g.off[bt.v];
+        bt.lb = (uint32_t)(g.off[bt.v + 1] - bt.boff);
+        bt.dla = bt.la;
+        bt.dlb = bt.lb;
+        bt.first = 2;  // a whole task
+      }
+    }
+    return true;
+  }
+}
+
+// Uniform view of the item a wavefront is working on.
+struct Item {
+  const uint32_t* A;
+  const uint32_t* B;
+  uint32_t la, lb, uq, vq, f, first, dla, dlb;
+  int64_t tid;
+};
+
+__device__ __forceinline__ void item_of(const Batch& bt, int it, const uint32_t* packed, Item& x) {
+  x.A = packed + (int64_t)bcast64((uint64_t)bt.aoff, it);
+  x.B = packed + (int64_t)bcast64((uint64_t)bt.boff, it);
+  x.la = bcast32(bt.la, it);
+  x.lb = bcast32(bt.lb, it);
+  x.uq = (bcast32(bt.u, it) << 2) | 3u;
+  x.vq = (bcast32(bt.v, it) << 2) | 3u;
+  x.f = bcast32(bt.f, it);
+  x.first = bcast32(bt.first, it);
+  x.dla = bcast32(bt.dla, it);
+  x.dlb = bcast32(bt.dlb, it);
+  x.tid = (int64_t)bcast64((uint64_t)bt.tid, it);
+}
+
+// Issue the global loads of one round's windows into registers (no wait).
+template <int W>
+__device__ __forceinline__ void load_round(const uint32_t* A, uint32_t na_ld, const uint32_t* B, uint32_t nb_ld,
+                                           int lane, uint32_t (&ra)[W / 64], uint32_t (&rb)[W / 64]) {
+#pragma unroll
+  for (int j = 0; j < W / 64; ++j)
+    if ((uint32_t)(j * 64) < na_ld) ra[j] = A[j * 64 + lane];
+#pragma unroll
+  for (int j = 0; j < W / 64; ++j)
+    if ((uint32_t)(j * 64) < nb_ld) rb[j] = B[j * 64 + lane];
+}
+
+// Per-lane two-pointer walk of the lane's merge-path range of one round:
+// one distinct w per step, classified in situ from its direction bits
+// (Fig. 5 steps 2.1.4-2.1.4.2, Sec. 6).
+template <int W>
+__device__ __forceinline__ uint32_t merge_round(WaveLds<W>& L, uint32_t na, uint32_t nb, uint32_t uq, uint32_t vq,
+                                                uint64_t slice, int lane) {
+  const uint32_t D = na + nb;
+  const uint32_t d0 = (uint32_t)(((uint64_t)lane * D) >> 6), d1 = (uint32_t)(((uint64_t)(lane + 1) * D) >> 6);
+  uint32_t lo = d0 > nb ? d0 - nb : 0, hi = d0 < na ? d0 : na;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (key_of(L.a[mid]) <= key_of(L.b[d0 - mid - 1])) lo = mid + 1; else hi = mid;
+  }
+  uint32_t i = lo, k = d0 - lo;
+  // an id shared by A[i-1] and B[k] was consumed with A[i-1] by a lane before
+  if (i > 0 && k < nb && key_of(L.a[i - 1]) == key_of(L.b[k])) ++k;
+  uint32_t a = L.a[i], b = L.b[k];
+  uint32_t both = 0;
+  while (i + k < d1) {
+    const uint32_t ea = a | 3u, eb = b | 3u;
+    const bool tA = ea <= eb, tB = eb <= ea;
+    const uint32_t w = ea < eb ? ea : eb;
+    // canonical selection (Fig. 5 step 2.1.4): v < w, or u < w < v with w not in N(u)
+    const bool counted = (w > vq) | ((w > uq) & !tA);
+    uint32_t idx = (tA ? (a & 3u) : 0u) | (tB ? ((b & 3u) << 2) : 0u);
+    idx = counted ? idx : 0u;  // class 0 collects the w this edge does not own
+    const uint32_t cls = (uint32_t)(slice >> (idx << 2)) & 15u;
+    atomicAdd(&L.hist[cls * 64 + lane], 1u);
+    both += (uint32_t)(tA & tB);
+    i += (uint32_t)tA;
+    k += (uint32_t)tB;
+    a = L.a[i];
+    b = L.b[k];
+  }
+  return both;
+}
+
+template <int W>
+__device__ void flush_wave(WaveLds<W>& L, int lane, unsigned long long* acc) {
+  wave_lds_sync();
   for (int c = 3; c < 16; ++c) {
-    uint64_t s = wave_sum64(L.hist[c * 64 + lane]);
+    const uint64_t s = wave_sum64(L.hist[c * 64 + lane]);
     L.hist[c * 64 + lane] = 0;
     if (lane == 0 && s) atomicAdd(&acc[c], (unsigned long long)s);
   }
+  L.hist[lane] = 0;
   wave_lds_sync();
 }
 
-template <int WAVES>
+// Persistent census kernel. Each wavefront claims batches of items and runs a
+// two-stage pipeline over "rounds": while round r is merged from LDS, the
+// global loads of round r+1 (same item, or the next item of the batch) are in
+// flight in registers.
+template <int WAVES, int W>
 __global__ void __launch_bounds__(WAVES * 64) k_census(CensusArgs g) {
-  __shared__ WaveLds lds[WAVES];
+  __shared__ WaveLds<W> lds[WAVES];
   if (*g.err) return;
   const int lane = threadIdx.x & 63;
-  WaveLds& L = lds[threadIdx.x >> 6];
+  WaveLds<W>& L = lds[threadIdx.x >> 6];
   for (int c = 0; c < 16; ++c) L.hist[c * 64 + lane] = 0;
   wave_lds_sync();
   uint64_t inter_asym = 0, inter_mut = 0;  // per lane
   uint64_t dy_asym = 0, dy_mut = 0;        // wave-uniform
-  uint64_t steps = 0;                      // bound on any lane's counter increments since the last flush
+  uint64_t steps = 0;  // bound on any lane's counter increments since the last flush
 
-  // ---- phase 1: chunks of hub tasks (merge-path partitions across wavefronts)
-  const int64_t hub_items = g.nhub ? g.hub_pre[g.nhub] : 0;
-  for (;;) {
-    uint64_t base = 0;
-    if (lane == 0) base = atomicAdd(&g.qctr[0], (unsigned long long)BATCH);
-    base = bcast64(base, 0);
-    if ((int64_t)base >= hub_items) break;
-    const int cnt = (int)min((int64_t)BATCH, hub_items - (int64_t)base);
-    // lane l resolves item base+l
-    int64_t aoff = 0, boff = 0;
-    uint32_t la = 0, lb = 0, u = 0, v = 0, f = 0, first = 0, dla = 0, dlb = 0;
-    if (lane < cnt) {
-      const int64_t item = (int64_t)base + lane;
-      int64_t lo = 0, hi = g.nhub;  // last h with hub_pre[h] <= item
-      while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (g.hub_pre[mid] <= item) lo = mid; else hi = mid;
-      }
-      const int64_t c = item - g.hub_pre[lo];
-      const uint64_t tk = g.tasks[g.hub_task[lo]] & ~HUB_BIT;
-      u = (uint32_t)(tk >> 32);
-      const int64_t au = g.off[u];
-      dla = (uint32_t)(g.off[u + 1] - au);
-      const uint32_t pv = g.packed[au + (uint32_t)tk];
-      v = pv >> 2;
-      f = pv & 3u;
-      const int64_t bv = g.off[v];
-      dlb = (uint32_t)(g.off[v + 1] - bv);
-      const uint32_t* Ag = g.packed + au;
-      const uint32_t* Bg = g.packed + bv;
-      const uint64_t Ltot = (uint64_t)dla + dlb;
-      const uint64_t d0 = (uint64_t)c * g.chunk, d1 = min(d0 + (uint64_t)g.chunk, Ltot);
-      uint32_t i0 = global_split(Ag, dla, Bg, dlb, (uint32_t)d0), k0 = (uint32_t)d0 - i0;
-      uint32_t i1 = global_split(Ag, dla, Bg, dlb, (uint32_t)d1), k1 = (uint32_t)d1 - i1;
-      if (i0 > 0 && k0 < dlb && key_of(Ag[i0 - 1]) == key_of(Bg[k0])) ++k0;
-      if (i1 > 0 && k1 < dlb && key_of(Ag[i1 - 1]) == key_of(Bg[k1])) ++k1;
-      if (k1 < k0) k1 = k0;
-      aoff = au + i0;
-      la = i1 - i0;
-      boff = bv + k0;
-      lb = k1 - k0;
-      first = c == 0;
-    }
-    for (int it = 0; it < cnt; ++it) {
-      const uint32_t su = bcast32(u, it), sv = bcast32(v, it), sf = bcast32(f, it);
-      const uint32_t sla = bcast32(la, it), slb = bcast32(lb, it);
-      const int64_t sao = (int64_t)bcast64((uint64_t)aoff, it), sbo = (int64_t)bcast64((uint64_t)boff, it);
-      uint64_t inter = 0;
-      merge_range(g.packed + sao, sla, g.packed + sbo, slb, (su << 2) | 3u, (sv << 2) | 3u, g.cls.s[sf], L, lane,
-                  inter);
-      if (sf == 3) inter_mut += inter; else inter_asym += inter;
-      if (bcast32(first, it)) {
-        const uint64_t dyad = (uint64_t)g.n - bcast32(dla, it) - bcast32(dlb, it);
-        if (sf == 3) dy_mut += dyad; else dy_asym += dyad;
-      }
-      steps += (sla + slb) / 64 + 2;
-      if (steps > (1ull << 30)) { flush_wave(L, lane, g.acc); steps = 0; }
-    }
+  int phase = 0;
+  Batch bt;
+  if (!fetch_batch(g, lane, phase, bt)) {
+    flush_wave(L, lane, g.acc);
+    return;
   }
+  int it = 0;
+  Item cur;
+  item_of(bt, it, g.packed, cur);
+  uint32_t ia = 0, ib = 0;          // position of the current round in the item
+  uint32_t item_inter = 0;          // per lane, current item
+  uint64_t t_start = g.cycles ? __builtin_amdgcn_s_memtime() : 0;
+  uint32_t ra[W / 64], rb[W / 64];
+  uint32_t na_ld = min(cur.la, (uint32_t)W), nb_ld = min(cur.lb, (uint32_t)W);
+  load_round<W>(cur.A, na_ld, cur.B, nb_ld, lane, ra, rb);
 
-  // ---- phase 2: whole tasks (hub tasks are skipped here)
   for (;;) {
-    uint64_t base = 0;
-    if (lane == 0) base = atomicAdd(&g.qctr[1], (unsigned long long)BATCH);
-    base = bcast64(base, 0);
-    if ((int64_t)base >= g.ntasks) break;
-    const int cnt = (int)min((int64_t)BATCH, g.ntasks - (int64_t)base);
-    int64_t aoff = 0, boff = 0, tid = 0;
-    uint32_t la = 0, lb = 0, u = 0, v = 0, f = 0, skip = 1;
-    if (lane < cnt) {
-      tid = g.order ? g.order[base + lane] : (int64_t)base + lane;
-      const uint64_t tk = g.tasks[tid];
-      skip = (tk & HUB_BIT) != 0;
-      u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
-      aoff = g.off[u];
-      la = (uint32_t)(g.off[u + 1] - aoff);
-      const uint32_t pv = g.packed[aoff + (uint32_t)tk];
-      v = pv >> 2;
-      f = pv & 3u;
-      boff = g.off[v];
-      lb = (uint32_t)(g.off[v + 1] - boff);
+    // ---- stage the loaded round in LDS
+#pragma unroll
+    for (int j = 0; j < W / 64; ++j) {
+      const uint32_t k = (uint32_t)(j * 64 + lane);
+      if ((uint32_t)(j * 64) < na_ld) L.a[k] = k < na_ld ? ra[j] : KEY_INF;
+      if ((uint32_t)(j * 64) < nb_ld) L.b[k] = k < nb_ld ? rb[j] : KEY_INF;
     }
-    for (int it = 0; it < cnt; ++it) {
-      if (bcast32(skip, it)) continue;
-      const uint32_t su = bcast32(u, it), sv = bcast32(v, it), sf = bcast32(f, it);
-      const uint32_t sla = bcast32(la, it), slb = bcast32(lb, it);
-      const int64_t sao = (int64_t)bcast64((uint64_t)aoff, it), sbo = (int64_t)bcast64((uint64_t)boff, it);
-      uint64_t t_start = 0;
-      if (g.cycles) t_start = __builtin_amdgcn_s_memtime();
-      uint64_t inter = 0;
-      merge_range(g.packed + sao, sla, g.packed + sbo, slb, (su << 2) | 3u, (sv << 2) | 3u, g.cls.s[sf], L, lane,
-                  inter);
-      if (sf == 3) inter_mut += inter; else inter_asym += inter;
-      const uint64_t dyad = (uint64_t)g.n - sla - slb;
-      if (sf == 3) dy_mut += dyad; else dy_asym += dyad;
+    wave_lds_sync();
+    // every element up to the smaller of the two window maxima is merged now
+    const uint32_t ra_rem = cur.la - ia, rb_rem = cur.lb - ib;
+    const uint32_t lastA = na_ld < ra_rem ? key_of(L.a[na_ld - 1]) : KEY_INF;
+    const uint32_t lastB = nb_ld < rb_rem ? key_of(L.b[nb_ld - 1]) : KEY_INF;
+    const uint32_t bound = lastA < lastB ? lastA : lastB;
+    uint32_t na = 0, nb = 0;
+#pragma unroll
+    for (int j = 0; j < W / 64; ++j) {
+      const uint32_t k = (uint32_t)(j * 64 + lane);
+      if ((uint32_t)(j * 64) < na_ld) na += (uint32_t)__popcll(__ballot(k < na_ld && key_of(ra[j]) <= bound));
+      if ((uint32_t)(j * 64) < nb_ld) nb += (uint32_t)__popcll(__ballot(k < nb_ld && key_of(rb[j]) <= bound));
+    }
+    if (lane == 0) {
+      L.a[na] = KEY_INF;  // sentinels: the walk never reads past them
+      L.b[nb] = KEY_INF;
+    }
+    // ---- choose and issue the next round
+    const bool item_done = (ia + na >= cur.la) && (ib + nb >= cur.lb);
+    Item nxt = cur;
+    uint32_t nia = ia + na, nib = ib + nb;
+    bool more = true;
+    if (item_done) {
+      nia = nib = 0;
+      int nit = it + 1;
+      // skip empty items (hub tasks in the task queue)
+      while (nit < bt.cnt && bcast32(bt.la, nit) + bcast32(bt.lb, nit) == 0) ++nit;
+      if (nit < bt.cnt) {
+        item_of(bt, nit, g.packed, nxt);
+        it = nit;
+      } else {
+        // batch exhausted: claim the next one (the current item is already in
+        // scalars, so bt can be overwritten; this latency is not hidden)
+        for (;;) {
+          more = fetch_batch(g, lane, phase, bt);
+          if (!more) break;
+          int k0 = 0;
+          while (k0 < bt.cnt && bcast32(bt.la, k0) + bcast32(bt.lb, k0) == 0) ++k0;
+          if (k0 < bt.cnt) {
+            it = k0;
+            item_of(bt, k0, g.packed, nxt);
+            break;
+          }
+        }
+      }
+    }
+    const uint32_t nna_ld = more ? min(nxt.la - nia, (uint32_t)W) : 0u;
+    const uint32_t nnb_ld = more ? min(nxt.lb - nib, (uint32_t)W) : 0u;
+    wave_lds_sync();
+    // ra/rb are consumed (counts done, LDS staged): refill them for the next round
+    if (more) load_round<W>(nxt.A + nia, nna_ld, nxt.B + nib, nnb_ld, lane, ra, rb);
+    // ---- merge this round from LDS
+    item_inter += merge_round<W>(L, na, nb, cur.uq, cur.vq, g.cls.s[cur.f], lane);
+    steps += (na + nb) / 32 + 4;
+    if (item_done) {
+      if (cur.f == 3) inter_mut += item_inter; else inter_asym += item_inter;
+      item_inter = 0;
+      if (cur.first) {
+        const uint64_t dyad = (uint64_t)g.n - cur.dla - cur.dlb;
+        if (cur.f == 3) dy_mut += dyad; else dy_asym += dyad;
+      }
       if (g.cycles) {
         const uint64_t t_end = __builtin_amdgcn_s_memtime();
-        const int64_t st = (int64_t)bcast64((uint64_t)tid, it);
-        if (lane == 0) g.cycles[st] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
+        if (lane == 0 && cur.first == 2) g.cycles[cur.tid] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
+        t_start = t_end;
       }
-      steps += (sla + slb) / 64 + 2;
       if (steps > (1ull << 30)) { flush_wave(L, lane, g.acc); steps = 0; }
     }
+    wave_lds_sync();
+    if (!more) break;
+    cur = nxt;
+    ia = nia;
+    ib = nib;
+    na_ld = nna_ld;
+    nb_ld = nnb_ld;
   }
   flush_wave(L, lane, g.acc);
-  const uint64_t ia = wave_sum64(inter_asym), im = wave_sum64(inter_mut);
+  const uint64_t sa = wave_sum64(inter_asym), sm = wave_sum64(inter_mut);
   if (lane == 0) {
-    atomicAdd(&g.acc[1], (unsigned long long)(dy_asym + ia));
-    atomicAdd(&g.acc[2], (unsigned long long)(dy_mut + im));
+    atomicAdd(&g.acc[1], (unsigned long long)(dy_asym + sa));
+    atomicAdd(&g.acc[2], (unsigned long long)(dy_mut + sm));
   }
 }
 
@@ -556,25 +647,49 @@ static int scan_excl(const int64_t* in, int64_t m, int64_t* out, Scratch& scratc
   return TRIAD_OK;
 }
 
-template <int WAVES>
-static void launch_census(const CensusArgs& a, int groups, hipStream_t s) {
-  k_census<WAVES><<<groups, WAVES * 64, 0, s>>>(a);
+// Kernel variants: LDS window of 512 or 1024 entries per list.
+enum Variant { V_W512 = 0, V_W1024 = 1, NUM_VARIANTS };
+
+template <int WAVES, int W>
+static hipError_t launch_t(const CensusArgs& a, int groups, hipStream_t s) {
+  k_census<WAVES, W><<<groups, WAVES * 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+template <int WAVES, int W>
+static int occ_t() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W>, WAVES * 64, 0) != hipSuccess)
+    return 1;
+  return per_cu < 1 ? 1 : per_cu;
 }
 
-static int census_groups(int waves, int requested) {
+static hipError_t launch_census(int waves, int variant, const CensusArgs& a, int groups, hipStream_t s) {
+  const bool big = variant == V_W1024;
+  switch (waves) {
+    case 1: return big ? launch_t<1, 1024>(a, groups, s) : launch_t<1, 512>(a, groups, s);
+    case 2: return big ? launch_t<2, 1024>(a, groups, s) : launch_t<2, 512>(a, groups, s);
+    default: return big ? launch_t<4, 1024>(a, groups, s) : launch_t<4, 512>(a, groups, s);
+  }
+}
+
+static int census_groups(int waves, int variant, int requested) {
   if (requested > 0) return requested;
   DeviceInfo di;
   if (device_info(&di) != TRIAD_OK) return 1024;
-  int per_cu = 0;
-  hipError_t e;
+  const bool big = variant == V_W1024;
+  int per_cu;
   switch (waves) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<1>, 64, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<2>, 128, 0); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<8>, 512, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<4>, 256, 0); break;
+    case 1: per_cu = big ? occ_t<1, 1024>() : occ_t<1, 512>(); break;
+    case 2: per_cu = big ? occ_t<2, 1024>() : occ_t<2, 512>(); break;
+    default: per_cu = big ? occ_t<4, 1024>() : occ_t<4, 512>(); break;
   }
-  if (e != hipSuccess || per_cu < 1) per_cu = 1;
   return di.cus * per_cu;
+}
+
+static int default_variant() {
+  const char* e = getenv("TRIAD_VARIANT");
+  if (e && *e >= '0' && *e < '0' + NUM_VARIANTS) return *e - '0';
+  return V_W512;
 }
 
 struct Events {
@@ -611,8 +726,8 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   if (!off || !d_out || (nnz > 0 && (!nbr || !flg))) return fail(TRIAD_EINVAL, "NULL pointer argument");
   if (o.validate < 0 || o.validate > 1) return fail(TRIAD_EINVAL, "validate must be 0 or 1");
   if (o.schedule < 0 || o.schedule > 2) return fail(TRIAD_EINVAL, "unknown schedule");
-  int waves = o.waves_per_group ? o.waves_per_group : 4;
-  if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(TRIAD_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+  int waves = o.waves_per_group ? o.waves_per_group : 1;
+  if (waves != 1 && waves != 2 && waves != 4) return fail(TRIAD_EINVAL, "waves_per_group must be 1, 2 or 4");
   const int64_t chunk = o.chunk > 0 ? o.chunk : 32768;
   const int64_t hub_thr = o.hub_threshold == 0 ? 65536 : o.hub_threshold;
   if (chunk < 256 || chunk > ((int64_t)1 << 30)) return fail(TRIAD_EINVAL, "chunk must be in [256, 2^30]");
@@ -638,7 +753,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     ALLOC(ntask, n);
     ALLOC(tpre, n + 1);
     ALLOC(rowmark, (nnz >> 5) + 1);
-    ALLOC(packed, nnz);
+    ALLOC(packed, nnz + PAD);
     k_fill_u32<<<grid_for((nnz >> 5) + 1, 256, 4096), 256, 0, s>>>(rowmark, (nnz >> 5) + 1, 0);
     k_rows<<<grid_for(n, 256), 256, 0, s>>>(n, nnz, off, nbr, ustart, ntask, rowmark, err);
     if (nnz > 0) {
@@ -705,13 +820,9 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.cycles = o.task_cycles;
     a.err = err;
     a.cls = class_slices();
-    const int groups = census_groups(waves, o.grid_groups);
-    switch (waves) {
-      case 1: launch_census<1>(a, groups, s); break;
-      case 2: launch_census<2>(a, groups, s); break;
-      case 8: launch_census<8>(a, groups, s); break;
-      default: launch_census<4>(a, groups, s); break;
-    }
+    const int variant = default_variant();
+    const int groups = census_groups(waves, variant, o.grid_groups);
+    HIPCHK(launch_census(waves, variant, a, groups, s));
     HIPCHK(hipGetLastError());
   }
   ev.rec(3, s);

@@ -72,7 +72,9 @@ ClassSlices class_slices() {
   ClassSlices cs{};
   for (unsigned f = 0; f < 4; ++f) {
     uint64_t s = 0;
-    for (unsigned idx = 0; idx < 16; ++idx) {
+    // idx 0 (w in neither list) never occurs for a counted w: it is the
+    // kernel's bin for the w a task does not own, mapped to class 0 (unused)
+    for (unsigned idx = 1; idx < 16; ++idx) {
       unsigned fa = idx & 3u, fb = idx >> 2;
       s |= (uint64_t)(classify_code(f | fa << 2 | fb << 4) & 15) << (4 * idx);
     }
