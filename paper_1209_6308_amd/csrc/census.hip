@@ -260,13 +260,16 @@ struct CensusArgs {
 constexpr int BATCH = 64;   // work items claimed per queue access
 constexpr int PAD = 1024;   // readable entries past the end of the packed array
 
-// Per-wavefront LDS: two sorted windows (plus a sentinel slot each) and
-// lane-private class counters.
-template <int W>
+// Per-wavefront LDS: two sorted windows (plus a sentinel slot each) and the
+// class counters, one per (class, lane). HH = true shares each counter between
+// lanes l and l+32, which the LDS serves in different halves of a wave64
+// access, halving the array.
+template <int W, bool HH>
 struct WaveLds {
+  static constexpr int COLS = HH ? 32 : 64;
   uint32_t a[W + 1];
   uint32_t b[W + 1];
-  uint32_t hist[16 * 64];  // [class][lane]
+  uint32_t hist[16 * COLS];  // [class][column]
 };
 
 // Merge-path split of the diagonal d of A (la) and B (lb) in global memory:
@@ -282,13 +285,15 @@ __device__ uint32_t global_split(const uint32_t* A, uint32_t la, const uint32_t*
 
 // One batch of work items, one item per lane (lane < cnt). An item merges
 // A = packed[aoff .. aoff+la) (a range of N(u)) with B = packed[boff ..
-// boff+lb) (a range of N(v)); `first` items (1 = chunk 0 of a split task,
-// 2 = a whole task) also add the dyadic count of their task, whose full list
-// lengths are dla, dlb.
+// boff+lb) (a range of N(v)). uf = u | kind << 30 with kind 0 = a later chunk
+// of a split task, 1 = its first chunk, 2 = a whole task; the first two kinds
+// also add their task's dyadic term dyad = n - d(u) - d(v) (Fig. 5 step
+// 2.1.3, completed by the intersection size). vf = v << 2 | f_uv.
 struct Batch {
   int cnt;
   int64_t aoff, boff, tid;
-  uint32_t la, lb, u, v, f, first, dla, dlb;
+  uint32_t la, lb, uf, vf;
+  int32_t dyad;
 };
 
 // Claims the next batch: hub chunks first (phase 0), then whole tasks
@@ -296,15 +301,21 @@ struct Batch {
 __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt) {
   const int64_t hub_items = g.nhub ? g.hub_pre[g.nhub] : 0;
   for (;;) {
-    if (phase == 0) {
-      uint64_t base = 0;
-      if (lane == 0) base = atomicAdd(&g.qctr[0], (unsigned long long)BATCH);
-      base = bcast64(base, 0);
-      if ((int64_t)base >= hub_items) { phase = 1; continue; }
-      bt.cnt = (int)min((int64_t)BATCH, hub_items - (int64_t)base);
-      bt.la = bt.lb = bt.u = bt.v = bt.f = bt.first = bt.dla = bt.dlb = 0;
-      bt.aoff = bt.boff = bt.tid = 0;
-      if (lane < bt.cnt) {
+    const int q = phase == 0 ? 0 : 1;
+    const int64_t limit = phase == 0 ? hub_items : g.ntasks;
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(&g.qctr[q], (unsigned long long)BATCH);
+    base = bcast64(base, 0);
+    if ((int64_t)base >= limit) {
+      if (phase == 0) { phase = 1; continue; }
+      return false;
+    }
+    bt.cnt = (int)min((int64_t)BATCH, limit - (int64_t)base);
+    bt.la = bt.lb = bt.uf = bt.vf = 0;
+    bt.dyad = 0;
+    bt.aoff = bt.boff = bt.tid = 0;
+    if (lane < bt.cnt) {
+      if (phase == 0) {
         const int64_t item = (int64_t)base + lane;
         int64_t lo = 0, hi = g.nhub;  // last h with hub_pre[h] <= item
         while (hi - lo > 1) {
@@ -314,55 +325,44 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
         const int64_t c = item - g.hub_pre[lo];
         bt.tid = (int64_t)g.hub_task[lo];
         const uint64_t tk = g.tasks[bt.tid] & ~HUB_BIT;
-        bt.u = (uint32_t)(tk >> 32);
-        const int64_t au = g.off[bt.u];
-        bt.dla = (uint32_t)(g.off[bt.u + 1] - au);
+        const uint32_t u = (uint32_t)(tk >> 32);
+        const int64_t au = g.off[u];
+        const uint32_t dla = (uint32_t)(g.off[u + 1] - au);
         const uint32_t pv = g.packed[au + (uint32_t)tk];
-        bt.v = pv >> 2;
-        bt.f = pv & 3u;
-        const int64_t bv = g.off[bt.v];
-        bt.dlb = (uint32_t)(g.off[bt.v + 1] - bv);
+        const int64_t bv = g.off[pv >> 2];
+        const uint32_t dlb = (uint32_t)(g.off[(pv >> 2) + 1] - bv);
         const uint32_t* Ag = g.packed + au;
         const uint32_t* Bg = g.packed + bv;
-        const uint64_t Ltot = (uint64_t)bt.dla + bt.dlb;
+        const uint64_t Ltot = (uint64_t)dla + dlb;
         const uint64_t d0 = (uint64_t)c * g.chunk, d1 = min(d0 + (uint64_t)g.chunk, Ltot);
-        const uint32_t i0 = global_split(Ag, bt.dla, Bg, bt.dlb, (uint32_t)d0);
-        const uint32_t i1 = global_split(Ag, bt.dla, Bg, bt.dlb, (uint32_t)d1);
+        const uint32_t i0 = global_split(Ag, dla, Bg, dlb, (uint32_t)d0);
+        const uint32_t i1 = global_split(Ag, dla, Bg, dlb, (uint32_t)d1);
         uint32_t k0 = (uint32_t)d0 - i0, k1 = (uint32_t)d1 - i1;
         // an id shared by A and B stays with the chunk holding its A copy
-        if (i0 > 0 && k0 < bt.dlb && key_of(Ag[i0 - 1]) == key_of(Bg[k0])) ++k0;
-        if (i1 > 0 && k1 < bt.dlb && key_of(Ag[i1 - 1]) == key_of(Bg[k1])) ++k1;
+        if (i0 > 0 && k0 < dlb && key_of(Ag[i0 - 1]) == key_of(Bg[k0])) ++k0;
+        if (i1 > 0 && k1 < dlb && key_of(Ag[i1 - 1]) == key_of(Bg[k1])) ++k1;
         if (k1 < k0) k1 = k0;
         bt.aoff = au + i0;
         bt.la = i1 - i0;
         bt.boff = bv + k0;
         bt.lb = k1 - k0;
-        bt.first = c == 0;
-      }
-      return true;
-    }
-    uint64_t base = 0;
-    if (lane == 0) base = atomicAdd(&g.qctr[1], (unsigned long long)BATCH);
-    base = bcast64(base, 0);
-    if ((int64_t)base >= g.ntasks) return false;
-    bt.cnt = (int)min((int64_t)BATCH, g.ntasks - (int64_t)base);
-    bt.la = bt.lb = bt.u = bt.v = bt.f = bt.first = bt.dla = bt.dlb = 0;
-    bt.aoff = bt.boff = bt.tid = 0;
-    if (lane < bt.cnt) {
-      bt.tid = g.order ? g.order[base + lane] : (int64_t)base + lane;
-      const uint64_t tk = g.tasks[bt.tid];
-      if (!(tk & HUB_BIT)) {  // hub tasks were merged in phase 0: empty item here
-        bt.u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
-        bt.aoff = g.off[bt.u];
-        bt.la = (uint32_t)(g.off[bt.u + 1] - bt.aoff);
-        const uint32_t pv = g.packed[bt.aoff + (uint32_t)tk];
-        bt.v = pv >> 2;
-        bt.f = pv & 3u;
-        bt.boff = g.off[bt.v];
-        bt.lb = (uint32_t)(g.off[bt.v + 1] - bt.boff);
-        bt.dla = bt.la;
-        bt.dlb = bt.lb;
-        bt.first = 2;  // a whole task
+        bt.uf = u | ((c == 0 ? 1u : 0u) << 30);
+        bt.vf = pv;
+        bt.dyad = c == 0 ? (int32_t)(g.n - (int64_t)dla - (int64_t)dlb) : 0;
+      } else {
+        bt.tid = g.order ? g.order[base + lane] : (int64_t)base + lane;
+        const uint64_t tk = g.tasks[bt.tid];
+        if (!(tk & HUB_BIT)) {  // hub tasks were merged in phase 0: empty item here
+          const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
+          bt.aoff = g.off[u];
+          bt.la = (uint32_t)(g.off[u + 1] - bt.aoff);
+          const uint32_t pv = g.packed[bt.aoff + (uint32_t)tk];
+          bt.boff = g.off[pv >> 2];
+          bt.lb = (uint32_t)(g.off[(pv >> 2) + 1] - bt.boff);
+          bt.uf = u | (2u << 30);
+          bt.vf = pv;
+          bt.dyad = (int32_t)(g.n - (int64_t)bt.la - (int64_t)bt.lb);
+        }
       }
     }
     return true;
@@ -373,7 +373,8 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
 struct Item {
   const uint32_t* A;
   const uint32_t* B;
-  uint32_t la, lb, uq, vq, f, first, dla, dlb;
+  uint32_t la, lb, uq, vq, f, kind;
+  int32_t dyad;
   int64_t tid;
 };
 
@@ -382,12 +383,12 @@ __device__ __forceinline__ void item_of(const Batch& bt, int it, const uint32_t*
   x.B = packed + (int64_t)bcast64((uint64_t)bt.boff, it);
   x.la = bcast32(bt.la, it);
   x.lb = bcast32(bt.lb, it);
-  x.uq = (bcast32(bt.u, it) << 2) | 3u;
-  x.vq = (bcast32(bt.v, it) << 2) | 3u;
-  x.f = bcast32(bt.f, it);
-  x.first = bcast32(bt.first, it);
-  x.dla = bcast32(bt.dla, it);
-  x.dlb = bcast32(bt.dlb, it);
+  const uint32_t uf = bcast32(bt.uf, it), vf = bcast32(bt.vf, it);
+  x.uq = (uf << 2) | 3u;  // the kind bits shift out
+  x.vq = vf | 3u;
+  x.f = vf & 3u;
+  x.kind = uf >> 30;
+  x.dyad = (int32_t)bcast32((uint32_t)bt.dyad, it);
   x.tid = (int64_t)bcast64((uint64_t)bt.tid, it);
 }
 
@@ -405,10 +406,11 @@ __device__ __forceinline__ void load_round(const uint32_t* A, uint32_t na_ld, co
 
 // Per-lane two-pointer walk of the lane's merge-path range of one round:
 // one distinct w per step, classified in situ from its direction bits
-// (Fig. 5 steps 2.1.4-2.1.4.2, Sec. 6).
-template <int W>
-__device__ __forceinline__ uint32_t merge_round(WaveLds<W>& L, uint32_t na, uint32_t nb, uint32_t uq, uint32_t vq,
-                                                uint64_t slice, int lane) {
+// (Fig. 5 steps 2.1.4-2.1.4.2, Sec. 6). Returns the number of ids found in
+// both lists (entries consumed minus steps taken).
+template <int W, bool HH>
+__device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
+                                                uint32_t vq, uint64_t slice, uint32_t col, int lane) {
   const uint32_t D = na + nb;
   const uint32_t d0 = (uint32_t)(((uint64_t)lane * D) >> 6), d1 = (uint32_t)(((uint64_t)(lane + 1) * D) >> 6);
   uint32_t lo = d0 > nb ? d0 - nb : 0, hi = d0 < na ? d0 : na;
@@ -419,70 +421,85 @@ __device__ __forceinline__ uint32_t merge_round(WaveLds<W>& L, uint32_t na, uint
   uint32_t i = lo, k = d0 - lo;
   // an id shared by A[i-1] and B[k] was consumed with A[i-1] by a lane before
   if (i > 0 && k < nb && key_of(L.a[i - 1]) == key_of(L.b[k])) ++k;
+  const uint32_t start = i + k;
   uint32_t a = L.a[i], b = L.b[k];
-  uint32_t both = 0;
+  uint32_t steps = 0;
   while (i + k < d1) {
     const uint32_t ea = a | 3u, eb = b | 3u;
     const bool tA = ea <= eb, tB = eb <= ea;
     const uint32_t w = ea < eb ? ea : eb;
     // canonical selection (Fig. 5 step 2.1.4): v < w, or u < w < v with w not in N(u)
     const bool counted = (w > vq) | ((w > uq) & !tA);
+    // 4-bit index fa | fb << 2 of the flags of w in N(u) and N(v); 0 when this
+    // edge does not own the triad
     uint32_t idx = (tA ? (a & 3u) : 0u) | (tB ? ((b & 3u) << 2) : 0u);
-    idx = counted ? idx : 0u;  // class 0 collects the w this edge does not own
+    idx = counted ? idx : 0u;
     const uint32_t cls = (uint32_t)(slice >> (idx << 2)) & 15u;
-    atomicAdd(&L.hist[cls * 64 + lane], 1u);
-    both += (uint32_t)(tA & tB);
+    atomicAdd(&L.hist[cls * WaveLds<W, HH>::COLS + col], 1u);
+    ++steps;
     i += (uint32_t)tA;
     k += (uint32_t)tB;
     a = L.a[i];
     b = L.b[k];
   }
-  return both;
+  return (i + k - start) - steps;
 }
 
-template <int W>
-__device__ void flush_wave(WaveLds<W>& L, int lane, unsigned long long* acc) {
+template <int W, bool HH>
+__device__ void flush_wave(WaveLds<W, HH>& L, int lane, unsigned long long* acc) {
+  constexpr int C = WaveLds<W, HH>::COLS;
   wave_lds_sync();
-  for (int c = 3; c < 16; ++c) {
-    const uint64_t s = wave_sum64(L.hist[c * 64 + lane]);
-    L.hist[c * 64 + lane] = 0;
-    if (lane == 0 && s) atomicAdd(&acc[c], (unsigned long long)s);
+  for (int c = 1; c < 16; ++c) {
+    const uint64_t x = lane < C ? L.hist[c * C + lane] : 0u;
+    const uint64_t sum = wave_sum64(x);
+    if (lane == 0 && sum) atomicAdd(&acc[c], (unsigned long long)sum);
   }
-  L.hist[lane] = 0;
+  for (int c = 0; c < 16; ++c)
+    if (lane < C) L.hist[c * C + lane] = 0;
   wave_lds_sync();
 }
 
 // Persistent census kernel. Each wavefront claims batches of items and runs a
 // two-stage pipeline over "rounds": while round r is merged from LDS, the
 // global loads of round r+1 (same item, or the next item of the batch) are in
-// flight in registers.
-template <int WAVES, int W>
-__global__ void __launch_bounds__(WAVES * 64) k_census(CensusArgs g) {
-  __shared__ WaveLds<W> lds[WAVES];
+// flight in registers. CYC adds per-task cycle recording.
+template <int WAVES, int W, bool HH, bool CYC, int MINW>
+__global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
+  __shared__ WaveLds<W, HH> lds[WAVES];
+  constexpr int C = WaveLds<W, HH>::COLS;
   if (*g.err) return;
   const int lane = threadIdx.x & 63;
-  WaveLds<W>& L = lds[threadIdx.x >> 6];
-  for (int c = 0; c < 16; ++c) L.hist[c * 64 + lane] = 0;
+  WaveLds<W, HH>& L = lds[threadIdx.x >> 6];
+  for (int c = 0; c < 16; ++c)
+    if (lane < C) L.hist[c * C + lane] = 0;
   wave_lds_sync();
-  uint64_t inter_asym = 0, inter_mut = 0;  // per lane
-  uint64_t dy_asym = 0, dy_mut = 0;        // wave-uniform
-  uint64_t steps = 0;  // bound on any lane's counter increments since the last flush
+  const uint32_t col = (uint32_t)(lane & (C - 1));
+  // counters 1 (012) and 2 (102) hold each lane's count of ids found in both
+  // lists, by the task's u-v dyad; the rest of those two classes is the
+  // wave-uniform n - d(u) - d(v) part
+  uint64_t dy_asym = 0, dy_mut = 0;
+  uint64_t steps = 0;  // bound on any counter's increments since the last flush
 
+  // The pipeline starts on an empty item: its round is a no-op that is
+  // immediately "done", so the first real item is claimed by the same code
+  // path as every later one.
   int phase = 0;
   Batch bt;
-  if (!fetch_batch(g, lane, phase, bt)) {
-    flush_wave(L, lane, g.acc);
-    return;
-  }
+  bt.cnt = 0;
   int it = 0;
   Item cur;
-  item_of(bt, it, g.packed, cur);
-  uint32_t ia = 0, ib = 0;          // position of the current round in the item
-  uint32_t item_inter = 0;          // per lane, current item
-  uint64_t t_start = g.cycles ? __builtin_amdgcn_s_memtime() : 0;
+  cur.A = cur.B = g.packed;
+  cur.la = cur.lb = 0;
+  cur.uq = cur.vq = 0;
+  cur.f = 1;
+  cur.kind = 0;
+  cur.dyad = 0;
+  cur.tid = 0;
+  uint32_t ia = 0, ib = 0;  // position of the current round in the item
+  uint32_t item_inter = 0;  // per lane, current item
+  uint64_t t_start = CYC ? __builtin_amdgcn_s_memtime() : 0;
   uint32_t ra[W / 64], rb[W / 64];
-  uint32_t na_ld = min(cur.la, (uint32_t)W), nb_ld = min(cur.lb, (uint32_t)W);
-  load_round<W>(cur.A, na_ld, cur.B, nb_ld, lane, ra, rb);
+  uint32_t na_ld = 0, nb_ld = 0;
 
   for (;;) {
     // ---- stage the loaded round in LDS
@@ -544,18 +561,17 @@ __global__ void __launch_bounds__(WAVES * 64) k_census(CensusArgs g) {
     // ra/rb are consumed (counts done, LDS staged): refill them for the next round
     if (more) load_round<W>(nxt.A + nia, nna_ld, nxt.B + nib, nnb_ld, lane, ra, rb);
     // ---- merge this round from LDS
-    item_inter += merge_round<W>(L, na, nb, cur.uq, cur.vq, g.cls.s[cur.f], lane);
-    steps += (na + nb) / 32 + 4;
+    item_inter += merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, g.cls.s[cur.f], col, lane);
+    steps += (na + nb) / (HH ? 16 : 32) + 4;
     if (item_done) {
-      if (cur.f == 3) inter_mut += item_inter; else inter_asym += item_inter;
+      atomicAdd(&L.hist[(cur.f == 3 ? 2 : 1) * C + col], item_inter);
       item_inter = 0;
-      if (cur.first) {
-        const uint64_t dyad = (uint64_t)g.n - cur.dla - cur.dlb;
-        if (cur.f == 3) dy_mut += dyad; else dy_asym += dyad;
+      if (cur.kind) {
+        if (cur.f == 3) dy_mut += (uint64_t)(int64_t)cur.dyad; else dy_asym += (uint64_t)(int64_t)cur.dyad;
       }
-      if (g.cycles) {
+      if constexpr (CYC) {
         const uint64_t t_end = __builtin_amdgcn_s_memtime();
-        if (lane == 0 && cur.first == 2) g.cycles[cur.tid] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
+        if (lane == 0 && cur.kind == 2) g.cycles[cur.tid] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
         t_start = t_end;
       }
       if (steps > (1ull << 30)) { flush_wave(L, lane, g.acc); steps = 0; }
@@ -569,10 +585,9 @@ __global__ void __launch_bounds__(WAVES * 64) k_census(CensusArgs g) {
     nb_ld = nnb_ld;
   }
   flush_wave(L, lane, g.acc);
-  const uint64_t sa = wave_sum64(inter_asym), sm = wave_sum64(inter_mut);
   if (lane == 0) {
-    atomicAdd(&g.acc[1], (unsigned long long)(dy_asym + sa));
-    atomicAdd(&g.acc[2], (unsigned long long)(dy_mut + sm));
+    atomicAdd(&g.acc[1], (unsigned long long)dy_asym);
+    atomicAdd(&g.acc[2], (unsigned long long)dy_mut);
   }
 }
 
@@ -647,49 +662,67 @@ static int scan_excl(const int64_t* in, int64_t m, int64_t* out, Scratch& scratc
   return TRIAD_OK;
 }
 
-// Kernel variants: LDS window of 512 or 1024 entries per list.
-enum Variant { V_W512 = 0, V_W1024 = 1, NUM_VARIANTS };
+// Kernel variants: LDS window per list x counter array layout x occupancy hint.
+enum Variant { V_W512 = 0, V_W1024 = 1, V_W512_HH = 2, V_W256_HH = 3, V_W512_HH6 = 4, NUM_VARIANTS };
 
-template <int WAVES, int W>
-static hipError_t launch_t(const CensusArgs& a, int groups, hipStream_t s) {
-  k_census<WAVES, W><<<groups, WAVES * 64, 0, s>>>(a);
+template <int WAVES, int W, bool HH, int MINW>
+static hipError_t launch_t(const CensusArgs& a, bool cyc, int groups, hipStream_t s) {
+  if (cyc) k_census<WAVES, W, HH, true, MINW><<<groups, WAVES * 64, 0, s>>>(a);
+  else k_census<WAVES, W, HH, false, MINW><<<groups, WAVES * 64, 0, s>>>(a);
   return hipGetLastError();
 }
-template <int WAVES, int W>
-static int occ_t() {
+template <int WAVES, int W, bool HH, int MINW>
+static int occ_t(bool cyc) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W>, WAVES * 64, 0) != hipSuccess)
-    return 1;
+  hipError_t e = cyc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W, HH, true, MINW>,
+                                                                     WAVES * 64, 0)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W, HH, false, MINW>,
+                                                                     WAVES * 64, 0);
+  if (e != hipSuccess) return 1;
   return per_cu < 1 ? 1 : per_cu;
+}
+template <int WAVES>
+static hipError_t launch_v(int variant, const CensusArgs& a, bool cyc, int groups, hipStream_t s) {
+  switch (variant) {
+    case V_W1024: return launch_t<WAVES, 1024, false, 1>(a, cyc, groups, s);
+    case V_W512_HH: return launch_t<WAVES, 512, true, 1>(a, cyc, groups, s);
+    case V_W256_HH: return launch_t<WAVES, 256, true, 1>(a, cyc, groups, s);
+    case V_W512_HH6: return launch_t<WAVES, 512, true, 6>(a, cyc, groups, s);
+    default: return launch_t<WAVES, 512, false, 1>(a, cyc, groups, s);
+  }
+}
+template <int WAVES>
+static int occ_v(int variant, bool cyc) {
+  switch (variant) {
+    case V_W1024: return occ_t<WAVES, 1024, false, 1>(cyc);
+    case V_W512_HH: return occ_t<WAVES, 512, true, 1>(cyc);
+    case V_W256_HH: return occ_t<WAVES, 256, true, 1>(cyc);
+    case V_W512_HH6: return occ_t<WAVES, 512, true, 6>(cyc);
+    default: return occ_t<WAVES, 512, false, 1>(cyc);
+  }
 }
 
 static hipError_t launch_census(int waves, int variant, const CensusArgs& a, int groups, hipStream_t s) {
-  const bool big = variant == V_W1024;
+  const bool cyc = a.cycles != nullptr;
   switch (waves) {
-    case 1: return big ? launch_t<1, 1024>(a, groups, s) : launch_t<1, 512>(a, groups, s);
-    case 2: return big ? launch_t<2, 1024>(a, groups, s) : launch_t<2, 512>(a, groups, s);
-    default: return big ? launch_t<4, 1024>(a, groups, s) : launch_t<4, 512>(a, groups, s);
+    case 1: return launch_v<1>(variant, a, cyc, groups, s);
+    case 2: return launch_v<2>(variant, a, cyc, groups, s);
+    default: return launch_v<4>(variant, a, cyc, groups, s);
   }
 }
 
-static int census_groups(int waves, int variant, int requested) {
+static int census_groups(int waves, int variant, bool cyc, int requested) {
   if (requested > 0) return requested;
   DeviceInfo di;
   if (device_info(&di) != TRIAD_OK) return 1024;
-  const bool big = variant == V_W1024;
-  int per_cu;
-  switch (waves) {
-    case 1: per_cu = big ? occ_t<1, 1024>() : occ_t<1, 512>(); break;
-    case 2: per_cu = big ? occ_t<2, 1024>() : occ_t<2, 512>(); break;
-    default: per_cu = big ? occ_t<4, 1024>() : occ_t<4, 512>(); break;
-  }
+  const int per_cu = waves == 1 ? occ_v<1>(variant, cyc) : waves == 2 ? occ_v<2>(variant, cyc) : occ_v<4>(variant, cyc);
   return di.cus * per_cu;
 }
 
 static int default_variant() {
   const char* e = getenv("TRIAD_VARIANT");
   if (e && *e >= '0' && *e < '0' + NUM_VARIANTS) return *e - '0';
-  return V_W512;
+  return V_W512_HH6;
 }
 
 struct Events {
@@ -821,7 +854,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.err = err;
     a.cls = class_slices();
     const int variant = default_variant();
-    const int groups = census_groups(waves, variant, o.grid_groups);
+    const int groups = census_groups(waves, variant, a.cycles != nullptr, o.grid_groups);
     HIPCHK(launch_census(waves, variant, a, groups, s));
     HIPCHK(hipGetLastError());
   }
