@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--schedule", default="plain", choices=["plain", "heuristic", "learned"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-schedules", action="store_true", help="skip the heuristic / learned comparison")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
@@ -108,27 +109,50 @@ def main():
     d_off, d_nbr, d_flg = triad.to_device(g, "cuda")
     d_out = torch.empty(17, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
-    kw = {"schedule": args.schedule}
-    if args.schedule == "learned":
-        from paper_1209_6308_amd import costmodel
-        kw["model"] = costmodel.load_or_train(stream=stream)
+    models = {}
 
-    for i in range(args.warmup):
-        triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream, d_out=d_out, **kw)
-        log(f"warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    census_ms, counts = [], None
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        counts, status, tm = triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream,
-                                                       d_out=d_out, **kw)
-        census_ms.append(tm["census_ms"])
-        log(f"step {i + 1}/{args.steps}: census kernel {tm['census_ms']:.1f} ms")
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    def run(schedule, steps, warmup, spans=False):
+        kw = {"schedule": schedule}
+        if schedule == "learned":
+            if "learned" not in models:
+                from paper_1209_6308_amd import costmodel
+                t0 = time.time()
+                models["learned"] = costmodel.load_or_train(stream=stream)
+                models["report"] = costmodel.last_training_report()
+                models["report"]["train_seconds"] = round(time.time() - t0, 1)
+                log(f"cost model trained: {models['report']}")
+            kw["model"] = models["learned"]
+        for i in range(warmup):
+            triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream, d_out=d_out, **kw)
+            log(f"{schedule}: warmup {i + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        census_ms, counts, tasks_ms = [], None, []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            counts, status, tm = triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream,
+                                                           d_out=d_out, **kw)
+            census_ms.append(tm["census_ms"])
+            tasks_ms.append(tm["tasks_ms"])
+            log(f"{schedule}: step {i + 1}/{steps}: census kernel {tm['census_ms']:.1f} ms")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out = {"wall_s": wall, "census_ms": census_ms, "tasks_ms": tasks_ms, "counts": counts, "waves": tm["waves"]}
+        if spans:
+            span = torch.zeros((tm["waves"], 2), dtype=torch.int64, device="cuda")
+            triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream, d_out=d_out, wave_span=span,
+                                      **kw)
+            sp = span.cpu().numpy().astype("float64")
+            busy = sp[:, 1] - sp[:, 0]
+            out["makespan_imbalance"] = float((sp[:, 1].max() - sp[:, 0].min()) / busy.mean() - 1.0)
+            out["wave_end_spread_ms"] = float((sp[:, 1].max() - sp[:, 1].min()) / 1e5)
+        return out
+
+    main = run(args.schedule, args.steps, args.warmup, spans=not args.no_schedules)
+    counts = main["counts"]
+    wall = main["wall_s"]
     ms_per_step = wall * 1e3 / args.steps
     value = st["m_sym"] * args.steps / wall
-    kern_s = sum(census_ms) / len(census_ms) / 1e3
+    kern_s = sum(main["census_ms"]) / len(main["census_ms"]) / 1e3
     b_alg = 4.25 * st["sum_d2"] + 32.0 * st["m_sym"]
     achieved = b_alg / kern_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -160,6 +184,30 @@ def main():
                    "census": [str(x) for x in counts]},
         "roofline": roof,
     }
+
+    def summary(r):
+        k = sum(r["census_ms"]) / len(r["census_ms"])
+        d = {"edge_pairs_per_s": round(st["m_sym"] * len(r["census_ms"]) / r["wall_s"], 1),
+             "census_kernel_ms": round(k, 2), "schedule_ms": round(sum(r["tasks_ms"]) / len(r["tasks_ms"]), 2),
+             "hbm_frac_alg": round(b_alg / (k / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if "makespan_imbalance" in r:
+            d["makespan_imbalance"] = round(r["makespan_imbalance"], 4)
+            d["wave_end_spread_ms"] = round(r["wave_end_spread_ms"], 3)
+        return d
+
+    if not args.no_schedules:
+        sched = {args.schedule: summary(main)}
+        for other in ("plain", "heuristic", "learned"):
+            if other == args.schedule:
+                continue
+            r = run(other, max(1, args.steps // 2), 1, spans=True)
+            if r["counts"] != counts:
+                raise SystemExit(f"schedule {other} changed the census")
+            sched[other] = summary(r)
+        sched["identical_counts"] = True
+        if "report" in models:
+            sched["cost_model"] = models["report"]
+        rec["schedules"] = sched
     if not args.no_cpu_baseline:
         log("timing the oracle on a task sample (host cores)")
         rec["cpu_baseline"] = cpu_baseline(g)

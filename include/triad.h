@@ -79,6 +79,7 @@ typedef struct triad_timing {
   int64_t tasks;     /* number of (u,v) tasks, u < v = symmetric edges */
   int64_t hub_tasks; /* tasks split across several wavefronts */
   int64_t items;     /* work items after splitting */
+  int64_t waves;     /* wavefronts of the persistent census launch */
 } triad_timing;
 
 /* Options (a zeroed struct gives the defaults). */
@@ -96,6 +97,12 @@ typedef struct triad_opts {
   triad_timing *timing;    /* optional host output */
   int32_t waves_per_group; /* wavefronts per workgroup (1, 2 or 4); 0 = default */
   int32_t grid_groups;     /* persistent grid size in workgroups; 0 = default */
+  int32_t kernel_variant;  /* census kernel variant (LDS window and counter layout),
+                              set by triad_batch_autotune; 0 = the default */
+  uint64_t *wave_span;     /* optional device buffer [waves][2]: real-time clock
+                              (s_memrealtime, 100 MHz) at each census wavefront's
+                              start and end; size it with timing->waves of a
+                              previous call or grid_groups * waves_per_group */
 } triad_opts;
 
 /* Census of one graph given by HOST pointers (copied to the device; the call

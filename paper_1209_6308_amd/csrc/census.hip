@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -25,15 +26,7 @@
 
 namespace triad {
 
-#define HIPCHK(x)                                                                     \
-  do {                                                                                \
-    hipError_t e_ = (x);                                                              \
-    if (e_ != hipSuccess)                                                             \
-      return fail(TRIAD_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));     \
-  } while (0)
-
 constexpr uint32_t KEY_INF = 0xFFFFFFFFu;  // larger than any key (ids < 2^30 - 1)
-constexpr uint64_t HUB_BIT = 1ull << 63;   // task moved to the hub list
 
 __device__ __forceinline__ uint32_t key_of(uint32_t p) { return p | 3u; }
 
@@ -253,6 +246,10 @@ struct CensusArgs {
   unsigned long long* qctr;  // [2]: hub items, tasks
   unsigned long long* acc;   // [16]
   uint32_t* cycles;          // optional per-task cycles
+  uint64_t* wave_span;       // optional [waves][2]: realtime at wave start, end
+  const uint32_t* grow;      // batched census: graph of each row
+  const int64_t* vbase;      // batched census: first row of each graph
+  unsigned long long* gout;  // batched census: [graphs][16] accumulators
   const uint32_t* err;
   ClassSlices cls;           // nibble idx = fa | fb << 2 -> class; idx 0 -> 0 (not counted)
 };
@@ -292,12 +289,13 @@ __device__ uint32_t global_split(const uint32_t* A, uint32_t la, const uint32_t*
 struct Batch {
   int cnt;
   int64_t aoff, boff, tid;
-  uint32_t la, lb, uf, vf;
+  uint32_t la, lb, uf, vf, gid;
   int32_t dyad;
 };
 
 // Claims the next batch: hub chunks first (phase 0), then whole tasks
 // (phase 1). Returns false when both queues are drained.
+template <bool BAT>
 __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt) {
   const int64_t hub_items = g.nhub ? g.hub_pre[g.nhub] : 0;
   for (;;) {
@@ -311,7 +309,7 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
       return false;
     }
     bt.cnt = (int)min((int64_t)BATCH, limit - (int64_t)base);
-    bt.la = bt.lb = bt.uf = bt.vf = 0;
+    bt.la = bt.lb = bt.uf = bt.vf = bt.gid = 0;
     bt.dyad = 0;
     bt.aoff = bt.boff = bt.tid = 0;
     if (lane < bt.cnt) {
@@ -348,7 +346,12 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
         bt.lb = k1 - k0;
         bt.uf = u | ((c == 0 ? 1u : 0u) << 30);
         bt.vf = pv;
-        bt.dyad = c == 0 ? (int32_t)(g.n - (int64_t)dla - (int64_t)dlb) : 0;
+        int64_t nn = g.n;
+        if (BAT) {
+          bt.gid = g.grow[u];
+          nn = g.vbase[bt.gid + 1] - g.vbase[bt.gid];
+        }
+        bt.dyad = c == 0 ? (int32_t)(nn - (int64_t)dla - (int64_t)dlb) : 0;
       } else {
         bt.tid = g.order ? g.order[base + lane] : (int64_t)base + lane;
         const uint64_t tk = g.tasks[bt.tid];
@@ -361,7 +364,12 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
           bt.lb = (uint32_t)(g.off[(pv >> 2) + 1] - bt.boff);
           bt.uf = u | (2u << 30);
           bt.vf = pv;
-          bt.dyad = (int32_t)(g.n - (int64_t)bt.la - (int64_t)bt.lb);
+          int64_t nn = g.n;
+          if (BAT) {
+            bt.gid = g.grow[u];
+            nn = g.vbase[bt.gid + 1] - g.vbase[bt.gid];
+          }
+          bt.dyad = (int32_t)(nn - (int64_t)bt.la - (int64_t)bt.lb);
         }
       }
     }
@@ -373,7 +381,7 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
 struct Item {
   const uint32_t* A;
   const uint32_t* B;
-  uint32_t la, lb, uq, vq, f, kind;
+  uint32_t la, lb, uq, vq, f, kind, gid;
   int32_t dyad;
   int64_t tid;
 };
@@ -389,6 +397,7 @@ __device__ __forceinline__ void item_of(const Batch& bt, int it, const uint32_t*
   x.f = vf & 3u;
   x.kind = uf >> 30;
   x.dyad = (int32_t)bcast32((uint32_t)bt.dyad, it);
+  x.gid = bcast32(bt.gid, it);
   x.tid = (int64_t)bcast64((uint64_t)bt.tid, it);
 }
 
@@ -462,14 +471,19 @@ __device__ void flush_wave(WaveLds<W, HH>& L, int lane, unsigned long long* acc)
 // Persistent census kernel. Each wavefront claims batches of items and runs a
 // two-stage pipeline over "rounds": while round r is merged from LDS, the
 // global loads of round r+1 (same item, or the next item of the batch) are in
-// flight in registers. CYC adds per-task cycle recording.
-template <int WAVES, int W, bool HH, bool CYC, int MINW>
+// flight in registers. MODE 1 adds per-task cycle recording; MODE 2 is the
+// batched census: every graph of the batch accumulates into its own counters
+// (a wavefront flushes its LDS counters when it moves to another graph).
+template <int WAVES, int W, bool HH, int MODE, int MINW>
 __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
+  constexpr bool CYC = MODE == 1, BAT = MODE == 2;
   __shared__ WaveLds<W, HH> lds[WAVES];
   constexpr int C = WaveLds<W, HH>::COLS;
   if (*g.err) return;
   const int lane = threadIdx.x & 63;
   WaveLds<W, HH>& L = lds[threadIdx.x >> 6];
+  const int64_t wave_id = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+  if (g.wave_span && lane == 0) g.wave_span[2 * wave_id] = __builtin_amdgcn_s_memrealtime();
   for (int c = 0; c < 16; ++c)
     if (lane < C) L.hist[c * C + lane] = 0;
   wave_lds_sync();
@@ -493,8 +507,10 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   cur.uq = cur.vq = 0;
   cur.f = 1;
   cur.kind = 0;
+  cur.gid = 0;
   cur.dyad = 0;
   cur.tid = 0;
+  uint32_t wg = 0xFFFFFFFFu;  // graph whose counters the wavefront holds (batched)
   uint32_t ia = 0, ib = 0;  // position of the current round in the item
   uint32_t item_inter = 0;  // per lane, current item
   uint64_t t_start = CYC ? __builtin_amdgcn_s_memtime() : 0;
@@ -543,7 +559,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
         // batch exhausted: claim the next one (the current item is already in
         // scalars, so bt can be overwritten; this latency is not hidden)
         for (;;) {
-          more = fetch_batch(g, lane, phase, bt);
+          more = fetch_batch<BAT>(g, lane, phase, bt);
           if (!more) break;
           int k0 = 0;
           while (k0 < bt.cnt && bcast32(bt.la, k0) + bcast32(bt.lb, k0) == 0) ++k0;
@@ -561,6 +577,18 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
     // ra/rb are consumed (counts done, LDS staged): refill them for the next round
     if (more) load_round<W>(nxt.A + nia, nna_ld, nxt.B + nib, nnb_ld, lane, ra, rb);
     // ---- merge this round from LDS
+    if (BAT && cur.gid != wg && cur.la + cur.lb > 0) {
+      if (wg != 0xFFFFFFFFu) {
+        flush_wave(L, lane, g.gout + 16 * (uint64_t)wg);
+        if (lane == 0) {
+          atomicAdd(&g.gout[16 * (uint64_t)wg + 1], (unsigned long long)dy_asym);
+          atomicAdd(&g.gout[16 * (uint64_t)wg + 2], (unsigned long long)dy_mut);
+        }
+        dy_asym = dy_mut = 0;
+        steps = 0;
+      }
+      wg = cur.gid;
+    }
     item_inter += merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, g.cls.s[cur.f], col, lane);
     steps += (na + nb) / (HH ? 16 : 32) + 4;
     if (item_done) {
@@ -574,7 +602,10 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
         if (lane == 0 && cur.kind == 2) g.cycles[cur.tid] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
         t_start = t_end;
       }
-      if (steps > (1ull << 30)) { flush_wave(L, lane, g.acc); steps = 0; }
+      if (steps > (1ull << 30)) {
+        flush_wave(L, lane, BAT ? g.gout + 16 * (uint64_t)wg : g.acc);
+        steps = 0;
+      }
     }
     wave_lds_sync();
     if (!more) break;
@@ -584,10 +615,15 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
     na_ld = nna_ld;
     nb_ld = nnb_ld;
   }
-  flush_wave(L, lane, g.acc);
+  unsigned long long* tgt = g.acc;
+  if (BAT) tgt = wg != 0xFFFFFFFFu ? g.gout + 16 * (uint64_t)wg : nullptr;
+  if (tgt) flush_wave(L, lane, tgt);
   if (lane == 0) {
-    atomicAdd(&g.acc[1], (unsigned long long)dy_asym);
-    atomicAdd(&g.acc[2], (unsigned long long)dy_mut);
+    if (tgt) {
+      atomicAdd(&tgt[1], (unsigned long long)dy_asym);
+      atomicAdd(&tgt[2], (unsigned long long)dy_mut);
+    }
+    if (g.wave_span) g.wave_span[2 * wave_id + 1] = __builtin_amdgcn_s_memrealtime();
   }
 }
 
@@ -621,32 +657,6 @@ static int grid_for(int64_t work, int threads, int cap = 65536) {
   return (int)g;
 }
 
-// Stream-ordered scratch: freed on destruction in stream order.
-struct Scratch {
-  hipStream_t s;
-  std::vector<void*> ptrs;
-  explicit Scratch(hipStream_t st) : s(st) {}
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, s);
-  }
-  template <class T>
-  hipError_t get(T** p, int64_t count) {
-    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMallocAsync((void**)p, bytes, s);
-    if (e == hipSuccess) ptrs.push_back(*p);
-    return e;
-  }
-};
-
-#define ALLOC(ptr, count)                                                                        \
-  do {                                                                                           \
-    hipError_t e_ = scratch.get(&(ptr), (count));                                                \
-    if (e_ != hipSuccess) {                                                                      \
-      (void)hipGetLastError();                                                                   \
-      return fail(TRIAD_ENOMEM, std::string("device allocation of ") + #ptr + " failed");       \
-    }                                                                                            \
-  } while (0)
-
 static int scan_excl(const int64_t* in, int64_t m, int64_t* out, Scratch& scratch, hipStream_t s) {
   const int64_t nb = (m + SCAN_B - 1) / SCAN_B;
   int64_t* bsum = nullptr;
@@ -666,23 +676,24 @@ static int scan_excl(const int64_t* in, int64_t m, int64_t* out, Scratch& scratc
 enum Variant { V_W512 = 0, V_W1024 = 1, V_W512_HH = 2, V_W256_HH = 3, V_W512_HH6 = 4, NUM_VARIANTS };
 
 template <int WAVES, int W, bool HH, int MINW>
-static hipError_t launch_t(const CensusArgs& a, bool cyc, int groups, hipStream_t s) {
-  if (cyc) k_census<WAVES, W, HH, true, MINW><<<groups, WAVES * 64, 0, s>>>(a);
-  else k_census<WAVES, W, HH, false, MINW><<<groups, WAVES * 64, 0, s>>>(a);
+static hipError_t launch_t(const CensusArgs& a, int mode, int groups, hipStream_t s) {
+  if (mode == 1) k_census<WAVES, W, HH, 1, MINW><<<groups, WAVES * 64, 0, s>>>(a);
+  else if (mode == 2) k_census<WAVES, W, HH, 2, MINW><<<groups, WAVES * 64, 0, s>>>(a);
+  else k_census<WAVES, W, HH, 0, MINW><<<groups, WAVES * 64, 0, s>>>(a);
   return hipGetLastError();
 }
 template <int WAVES, int W, bool HH, int MINW>
-static int occ_t(bool cyc) {
+static int occ_t(int mode) {
   int per_cu = 0;
-  hipError_t e = cyc ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W, HH, true, MINW>,
-                                                                     WAVES * 64, 0)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W, HH, false, MINW>,
-                                                                     WAVES * 64, 0);
+  hipError_t e;
+  if (mode == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W, HH, 1, MINW>, WAVES * 64, 0);
+  else if (mode == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W, HH, 2, MINW>, WAVES * 64, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<WAVES, W, HH, 0, MINW>, WAVES * 64, 0);
   if (e != hipSuccess) return 1;
   return per_cu < 1 ? 1 : per_cu;
 }
 template <int WAVES>
-static hipError_t launch_v(int variant, const CensusArgs& a, bool cyc, int groups, hipStream_t s) {
+static hipError_t launch_v(int variant, const CensusArgs& a, int cyc, int groups, hipStream_t s) {
   switch (variant) {
     case V_W1024: return launch_t<WAVES, 1024, false, 1>(a, cyc, groups, s);
     case V_W512_HH: return launch_t<WAVES, 512, true, 1>(a, cyc, groups, s);
@@ -692,7 +703,7 @@ static hipError_t launch_v(int variant, const CensusArgs& a, bool cyc, int group
   }
 }
 template <int WAVES>
-static int occ_v(int variant, bool cyc) {
+static int occ_v(int variant, int cyc) {
   switch (variant) {
     case V_W1024: return occ_t<WAVES, 1024, false, 1>(cyc);
     case V_W512_HH: return occ_t<WAVES, 512, true, 1>(cyc);
@@ -703,7 +714,7 @@ static int occ_v(int variant, bool cyc) {
 }
 
 static hipError_t launch_census(int waves, int variant, const CensusArgs& a, int groups, hipStream_t s) {
-  const bool cyc = a.cycles != nullptr;
+  const int cyc = a.gout ? 2 : a.cycles ? 1 : 0;
   switch (waves) {
     case 1: return launch_v<1>(variant, a, cyc, groups, s);
     case 2: return launch_v<2>(variant, a, cyc, groups, s);
@@ -711,7 +722,7 @@ static hipError_t launch_census(int waves, int variant, const CensusArgs& a, int
   }
 }
 
-static int census_groups(int waves, int variant, bool cyc, int requested) {
+static int census_groups(int waves, int variant, int cyc, int requested) {
   if (requested > 0) return requested;
   DeviceInfo di;
   if (device_info(&di) != TRIAD_OK) return 1024;
@@ -835,14 +846,21 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
       }
     }
   }
+  int64_t* order = nullptr;
+  if (ntasks > 0 && o.schedule != TRIAD_SCHED_PLAIN) {
+    ALLOC(order, ntasks);
+    const int mode = (o.schedule == TRIAD_SCHED_LEARNED && o.model) ? 2 : 1;
+    if (int st = build_order(mode, o.model, n, off, packed, tasks, ntasks, order, scratch, s)) return st;
+  }
   ev.rec(2, s);
+  int groups = 0;
   if (ntasks > 0) {
     CensusArgs a{};
     a.n = n;
     a.off = off;
     a.packed = packed;
     a.tasks = tasks;
-    a.order = nullptr;
+    a.order = order;
     a.ntasks = ntasks;
     a.hub_task = hub_task;
     a.hub_pre = hub_pre;
@@ -851,10 +869,11 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.qctr = acc + 16;
     a.acc = acc;
     a.cycles = o.task_cycles;
+    a.wave_span = o.wave_span;
     a.err = err;
     a.cls = class_slices();
-    const int variant = default_variant();
-    const int groups = census_groups(waves, variant, a.cycles != nullptr, o.grid_groups);
+    const int variant = o.kernel_variant > 0 && o.kernel_variant <= NUM_VARIANTS ? o.kernel_variant - 1 : default_variant();
+    groups = census_groups(waves, variant, a.cycles != nullptr ? 1 : 0, o.grid_groups);
     HIPCHK(launch_census(waves, variant, a, groups, s));
     HIPCHK(hipGetLastError());
   }
@@ -874,8 +893,219 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     o.timing->tasks = ntasks;
     o.timing->hub_tasks = nhub;
     o.timing->items = ntasks;
+    o.timing->waves = (int64_t)groups * waves;
   }
   return chi ? TRIAD_OK_003_WRAPPED : TRIAD_OK;
+}
+
+
+// ---------------------------------------------------------------- batches
+// G graphs in one concatenated CSR (rows of graph g: [vbase[g], vbase[g+1]),
+// graph-local neighbour ids). Rebasing every id by vbase[g] turns the batch
+// into one disjoint union; a task never leaves its graph, so the single-graph
+// kernels apply unchanged except that each graph keeps its own counters.
+
+// Per row (thread per row): graph of the row, offset checks, local id checks,
+// packed words with global ids, first entry above the row, task count.
+__global__ void k_rows_batch(int32_t G, int64_t nv, int64_t nnz, const int64_t* __restrict__ vbase,
+                             const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                             const uint8_t* __restrict__ flg, uint32_t* __restrict__ grow,
+                             uint32_t* __restrict__ ustart, int64_t* __restrict__ ntask, uint32_t* __restrict__ packed,
+                             uint32_t* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < nv; u += stride) {
+    uint32_t bits = 0;
+    int32_t lo = 0, hi = G;  // last graph with vbase[g] <= u
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (vbase[mid] <= u) lo = mid; else hi = mid;
+    }
+    const int64_t g0 = vbase[lo], ng = vbase[lo + 1] - g0;
+    grow[u] = (uint32_t)lo;
+    const int64_t b = off[u], e = off[u + 1];
+    if (u == 0 && b != 0) bits |= ERR_RANGE;
+    if (u == nv - 1 && e != nnz) bits |= ERR_RANGE;
+    ustart[u] = 0;
+    ntask[u] = 0;
+    if (e < b || b < 0 || e > nnz) {
+      atomicOr(err, bits | ERR_RANGE);
+      continue;
+    }
+    const int32_t ul = (int32_t)(u - g0);
+    int64_t first = e;
+    int32_t prev = -1;
+    for (int64_t j = b; j < e; ++j) {
+      const int32_t y = nbr[j];
+      const uint32_t f = (flg[j >> 2] >> (2 * (j & 3))) & 3u;
+      if (y < 0 || y >= ng || f == 0) { bits |= ERR_RANGE; break; }
+      if (y <= prev) bits |= ERR_UNSORTED;
+      if (y == ul) bits |= ERR_SELFLOOP;
+      if (y > ul && first == e) first = j;
+      prev = y;
+      packed[j] = ((uint32_t)(y + g0) << 2) | f;
+    }
+    ustart[u] = (uint32_t)(first - b);
+    ntask[u] = e - first;
+    if (bits) atomicOr(err, bits);
+  }
+}
+
+__global__ void k_check_tasks(const int64_t* __restrict__ tpre, int64_t nv, int64_t nnz, uint32_t* __restrict__ err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && tpre[nv] * 2 != nnz) atomicOr(err, ERR_ASYM);
+}
+
+// Per graph: 003 = C(n_g, 3) minus the rest (n_g < 4,801,281 keeps C(n_g,3) < 2^64).
+__global__ void k_finalize_batch(int32_t G, const int64_t* __restrict__ vbase, unsigned long long* __restrict__ gout,
+                                 const uint32_t* __restrict__ err) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G || *err) return;
+  const uint64_t n = (uint64_t)(vbase[g + 1] - vbase[g]);
+  uint64_t c3 = 0;
+  if (n >= 3) {
+    // n(n-1)(n-2)/6 without overflow: divide the factors first
+    uint64_t a = n, b = n - 1, c = n - 2;
+    if (a % 2 == 0) a /= 2; else b /= 2;
+    if (a % 3 == 0) a /= 3; else if (b % 3 == 0) b /= 3; else c /= 3;
+    c3 = a * b * c;
+  }
+  uint64_t s = 0;
+  for (int k = 1; k < 16; ++k) s += gout[16 * (uint64_t)g + k];
+  gout[16 * (uint64_t)g] = c3 - s;
+}
+
+// Three-pass exclusive scan with caller-provided block sums (capturable).
+static void scan_excl_pre(const int64_t* in, int64_t m, int64_t* out, int64_t* bsum, hipStream_t s) {
+  const int64_t nb = (m + SCAN_B - 1) / SCAN_B;
+  if (m > 0) {
+    k_scan_sums<<<(unsigned)nb, SCAN_T, 0, s>>>(in, m, bsum);
+    k_scan_top<<<1, SCAN_T, 0, s>>>(bsum, nb);
+    k_scan_apply<<<(unsigned)nb, SCAN_T, 0, s>>>(in, m, bsum, out);
+  } else {
+    k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)out, 1, 0);
+  }
+}
+
+}  // namespace triad
+
+struct triad_batch_plan {
+  int32_t G = 0;
+  int64_t nv = 0, nnz = 0;
+  const int64_t* vbase = nullptr;
+  uint64_t* out = nullptr;
+  std::vector<void*> bufs;
+  uint32_t* err = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last = nullptr;
+  int launched = 0;
+};
+
+namespace triad {
+
+static void plan_free(triad_batch_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (void* b : p->bufs) (void)hipFree(b);
+  delete p;
+}
+
+template <class T>
+static hipError_t plan_alloc(triad_batch_plan* p, T** ptr, int64_t count) {
+  hipError_t e = hipMalloc((void**)ptr, (size_t)std::max<int64_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) p->bufs.push_back(*ptr);
+  return e;
+}
+
+static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, const int64_t* off, const int32_t* nbr,
+                      const uint8_t* flg, uint64_t* d_out, const triad_opts* opts, hipStream_t s,
+                      triad_batch_plan** out_plan) {
+  triad_opts o{};
+  if (opts) o = *opts;
+  if (G < 1 || nv < 0 || nv >= ((int64_t)1 << 30) || nnz < 0 || nnz >= ((int64_t)1 << 40))
+    return fail(TRIAD_EINVAL, "bad batch sizes");
+  if (!vbase || !off || !d_out || (nnz > 0 && (!nbr || !flg)) || !out_plan) return fail(TRIAD_EINVAL, "NULL pointer");
+  int waves = o.waves_per_group ? o.waves_per_group : 1;
+  if (waves != 1 && waves != 2 && waves != 4) return fail(TRIAD_EINVAL, "waves_per_group must be 1, 2 or 4");
+  const int variant = o.kernel_variant > 0 && o.kernel_variant <= NUM_VARIANTS ? o.kernel_variant - 1 : default_variant();
+  DeviceInfo di;
+  if (int st = device_info(&di)) return st;
+  triad_batch_plan* p = new triad_batch_plan;
+  p->G = G;
+  p->nv = nv;
+  p->nnz = nnz;
+  p->vbase = vbase;
+  p->out = d_out;
+  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr;
+  int64_t *ntask = nullptr, *tpre = nullptr, *bsum = nullptr;
+  uint64_t* tasks = nullptr;
+  unsigned long long* q = nullptr;
+  const int64_t ntasks = nnz / 2;
+  if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 2) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
+      plan_alloc(p, &ntask, nv) || plan_alloc(p, &tpre, nv + 1) || plan_alloc(p, &bsum, nv / SCAN_B + 2) ||
+      plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks)) {
+    plan_free(p);
+    (void)hipGetLastError();
+    return fail(TRIAD_ENOMEM, "device allocation for the batch plan failed");
+  }
+  CensusArgs a{};
+  a.n = 0;
+  a.off = off;
+  a.packed = packed;
+  a.tasks = tasks;
+  a.order = nullptr;
+  a.ntasks = ntasks;
+  a.hub_task = nullptr;
+  a.hub_pre = nullptr;
+  a.nhub = 0;
+  a.chunk = 1;
+  a.qctr = q;
+  a.acc = (unsigned long long*)d_out;
+  a.cycles = nullptr;
+  a.wave_span = nullptr;
+  a.grow = grow;
+  a.vbase = vbase;
+  a.gout = (unsigned long long*)d_out;
+  a.err = p->err;
+  a.cls = class_slices();
+  const int groups = census_groups(waves, variant, 2, o.grid_groups);
+  // capture the whole batched census as one graph (fills instead of memsets)
+  // on a private stream: the caller's stream may be the legacy null stream,
+  // which cannot be captured; launches replay it on the caller's stream
+  (void)s;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    if (cs) (void)hipStreamDestroy(cs);
+    plan_free(p);
+    return fail(TRIAD_EDEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  s = cs;
+  k_fill_u32<<<1, 64, 0, s>>>(p->err, 1, 0);
+  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)q, 2, 0);
+  k_fill_u64<<<grid_for((int64_t)G * 16, 256, 4096), 256, 0, s>>>(d_out, (int64_t)G * 16, 0);
+  if (nv > 0) {
+    k_rows_batch<<<grid_for(nv, 256, 65535), 256, 0, s>>>(G, nv, nnz, vbase, off, nbr, flg, grow, ustart, ntask, packed,
+                                                          p->err);
+    scan_excl_pre(ntask, nv, tpre, bsum, s);
+    k_check_tasks<<<1, 64, 0, s>>>(tpre, nv, nnz, p->err);
+    if (ntasks > 0) {
+      k_emit<<<grid_for(nv * 64, 256, 32768), 256, 0, s>>>(nv, off, packed, ustart, tpre, tasks, -1, 1, nullptr,
+                                                           nullptr, nullptr, p->err);
+      (void)launch_census(waves, variant, a, groups, s);
+    }
+  }
+  k_finalize_batch<<<(G + 255) / 256, 256, 0, s>>>(G, vbase, (unsigned long long*)d_out, p->err);
+  e = hipStreamEndCapture(s, &p->graph);
+  if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) {
+    plan_free(p);
+    return fail(TRIAD_EDEVICE, std::string("batch graph capture failed: ") + hipGetErrorString(e));
+  }
+  *out_plan = p;
+  return TRIAD_OK;
 }
 
 }  // namespace triad
@@ -939,6 +1169,131 @@ int triad_census_ex(int64_t n, const int64_t* off, const int32_t* nbr, const uin
 
 int triad_census(int64_t n, const int64_t* off, const int32_t* nbr, const uint8_t* flg, uint64_t out_u64[16]) {
   return triad_census_ex(n, off, nbr, flg, nullptr, out_u64, nullptr);
+}
+
+
+int triad_batch_plan_create(int32_t G, int64_t nv, int64_t nnz, const int64_t* d_vbase, const int64_t* d_offsets,
+                            const int32_t* d_nbrs, const uint8_t* d_flags, uint64_t* d_out, const triad_opts* opts,
+                            void* hip_stream, triad_batch_plan** plan) {
+  return plan_build(G, nv, nnz, d_vbase, d_offsets, d_nbrs, d_flags, d_out, opts, (hipStream_t)hip_stream, plan);
+}
+
+int triad_batch_plan_launch(triad_batch_plan* plan, void* hip_stream) {
+  if (!plan || !plan->exec) return fail(TRIAD_EINVAL, "invalid plan");
+  hipStream_t s = (hipStream_t)hip_stream;
+  HIPCHK(hipGraphLaunch(plan->exec, s));
+  plan->last = s;
+  plan->launched = 1;
+  return TRIAD_OK;
+}
+
+int triad_batch_plan_status(triad_batch_plan* plan) {
+  if (!plan) return fail(TRIAD_EINVAL, "invalid plan");
+  if (!plan->launched) return fail(TRIAD_EINVAL, "plan not launched");
+  HIPCHK(hipStreamSynchronize(plan->last));
+  uint32_t e = 0;
+  HIPCHK(hipMemcpy(&e, plan->err, sizeof(e), hipMemcpyDeviceToHost));
+  if (e) return fail(status_from_bits(e), "batch input validation failed on the device");
+  return TRIAD_OK;
+}
+
+void triad_batch_plan_destroy(triad_batch_plan* plan) { plan_free(plan); }
+
+int triad_census_batch(int32_t G, int64_t nv, int64_t nnz, const int64_t* d_vbase, const int64_t* d_offsets,
+                       const int32_t* d_nbrs, const uint8_t* d_flags, const triad_opts* opts, void* hip_stream,
+                       uint64_t* d_out) {
+  triad_batch_plan* p = nullptr;
+  if (int st = triad_batch_plan_create(G, nv, nnz, d_vbase, d_offsets, d_nbrs, d_flags, d_out, opts, hip_stream, &p))
+    return st;
+  int st = triad_batch_plan_launch(p, hip_stream);
+  if (st == TRIAD_OK) st = triad_batch_plan_status(p);
+  triad_batch_plan_destroy(p);
+  return st;
+}
+
+int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t* d_vbase, const int64_t* d_offsets,
+                         const int32_t* d_nbrs, const uint8_t* d_flags, void* hip_stream, const char* cache_path,
+                         triad_opts* best) {
+  if (!best) return fail(TRIAD_EINVAL, "best is NULL");
+  DeviceInfo di;
+  if (int st = device_info(&di)) return st;
+  char sig[160];
+  snprintf(sig, sizeof sig, "%s|G=%d|nv=%lld|nnz=%lld", di.name.c_str(), (int)G, (long long)nv, (long long)nnz);
+  // cache: one JSON object per line: {"sig": "...", "kernel_variant": k, "waves_per_group": w, "grid_groups": g, "ms": t}
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "r")) {
+      char line[512];
+      while (fgets(line, sizeof line, f)) {
+        char want[200];
+        snprintf(want, sizeof want, "\"sig\": \"%s\"", sig);
+        if (!strstr(line, want)) continue;
+        int kv = 0, wv = 0, gg = 0;
+        const char* p1 = strstr(line, "\"kernel_variant\": ");
+        const char* p2 = strstr(line, "\"waves_per_group\": ");
+        const char* p3 = strstr(line, "\"grid_groups\": ");
+        if (p1 && p2 && p3 && sscanf(p1 + 18, "%d", &kv) == 1 && sscanf(p2 + 19, "%d", &wv) == 1 &&
+            sscanf(p3 + 15, "%d", &gg) == 1) {
+          *best = triad_opts{};
+          best->kernel_variant = kv;
+          best->waves_per_group = wv;
+          best->grid_groups = gg;
+          fclose(f);
+          return TRIAD_OK;
+        }
+      }
+      fclose(f);
+    }
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  uint64_t* out = nullptr;
+  HIPCHK(hipMalloc(&out, sizeof(uint64_t) * 16 * (size_t)G));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  triad_opts bo{};
+  const int variants[3] = {V_W512_HH6 + 1, V_W512 + 1, V_W512_HH + 1};
+  const int wavess[2] = {1, 2};
+  int status = TRIAD_OK;
+  for (int vi = 0; vi < 3 && status == TRIAD_OK; ++vi)
+    for (int wi = 0; wi < 2 && status == TRIAD_OK; ++wi)
+      for (int gm = 1; gm <= 2; ++gm) {
+        triad_opts o{};
+        o.kernel_variant = variants[vi];
+        o.waves_per_group = wavess[wi];
+        o.grid_groups = census_groups(o.waves_per_group, variants[vi] - 1, 2, 0) * gm;
+        triad_batch_plan* p = nullptr;
+        status = triad_batch_plan_create(G, nv, nnz, d_vbase, d_offsets, d_nbrs, d_flags, out, &o, hip_stream, &p);
+        if (status != TRIAD_OK) break;
+        float t = 1e30f;
+        for (int rep = 0; rep < 3 && status == TRIAD_OK; ++rep) {
+          (void)hipEventRecord(e0, s);
+          status = triad_batch_plan_launch(p, hip_stream);
+          (void)hipEventRecord(e1, s);
+          if (status == TRIAD_OK) status = triad_batch_plan_status(p);
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0 && ms < t) t = ms;  // first launch is a warm-up
+        }
+        triad_batch_plan_destroy(p);
+        if (status == TRIAD_OK && t < best_ms) {
+          best_ms = t;
+          bo = o;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  if (status != TRIAD_OK) return status;
+  *best = bo;
+  if (cache_path) {
+    if (FILE* f = fopen(cache_path, "a")) {
+      fprintf(f, "{\"sig\": \"%s\", \"kernel_variant\": %d, \"waves_per_group\": %d, \"grid_groups\": %d, \"ms\": %.3f}\n",
+              sig, bo.kernel_variant, bo.waves_per_group, bo.grid_groups, best_ms);
+      fclose(f);
+    }
+  }
+  return TRIAD_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,450 @@
+// Task scheduling for the census: cost keys (d(u)+d(v), or a learned FP32
+// cost model), counting sort of the tasks into cost bins, longest first.
+//
+// Cost model: multilayer perceptron 6 -> 32 -> 32 -> 1, ReLU hidden layers,
+// trained on the GPU by the kernels below (forward, mean-squared-error
+// gradient by backpropagation, Adam) on per-task cycle counts recorded by the
+// census kernel itself. Parameter layout (TRIAD_MLP_PARAMS floats):
+//   W1[32][6] | b1[32] | W2[32][32] | b2[32] | W3[32] | b3
+// Features of task (u,v), each log2(1 + x): d(u), d(v), d(u)+d(v),
+// min(d(u),d(v)), max(d(u),d(v)), entries of N(u) above v.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "triad_internal.h"
+
+namespace triad {
+
+constexpr int NI = TRIAD_MLP_IN, NH = TRIAD_MLP_HIDDEN, NP = TRIAD_MLP_PARAMS;
+constexpr int OW1 = 0, OB1 = OW1 + NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH, OB3 = OW3 + NH;
+static_assert(OB3 + 1 == NP, "parameter layout");
+
+__device__ __forceinline__ void task_features(uint32_t du, uint32_t dv, uint32_t above, float x[NI]) {
+  const uint32_t mn = du < dv ? du : dv, mx = du < dv ? dv : du;
+  x[0] = log2f(1.0f + (float)du);
+  x[1] = log2f(1.0f + (float)dv);
+  x[2] = log2f(1.0f + (float)du + (float)dv);
+  x[3] = log2f(1.0f + (float)mn);
+  x[4] = log2f(1.0f + (float)mx);
+  x[5] = log2f(1.0f + (float)above);
+}
+
+// y = W3 . relu(W2 relu(W1 x + b1) + b2) + b3, weights w in LDS.
+__device__ __forceinline__ float mlp_forward(const float* w, const float x[NI]) {
+  float h1[NH];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    float a = w[OB1 + j];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) a = fmaf(w[OW1 + j * NI + i], x[i], a);
+    h1[j] = a > 0.0f ? a : 0.0f;
+  }
+  float y = w[OB3];
+#pragma unroll 1
+  for (int j = 0; j < NH; ++j) {
+    float a = w[OB2 + j];
+#pragma unroll
+    for (int k = 0; k < NH; ++k) a = fmaf(w[OW2 + j * NH + k], h1[k], a);
+    y = fmaf(w[OW3 + j], a > 0.0f ? a : 0.0f, y);
+  }
+  return y;
+}
+
+__device__ __forceinline__ void load_weights(const float* __restrict__ gw, float* sw) {
+  for (int p = threadIdx.x; p < NP; p += blockDim.x) sw[p] = gw[p];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- features
+
+// Features of every task, tasks in CSR order (raw CSR input).
+__global__ void k_features_csr(int64_t n, const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                               const int64_t* __restrict__ tpre, float* __restrict__ feat) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t u = wave; u < n; u += nwave) {
+    const int64_t b = off[u];
+    const uint32_t du = (uint32_t)(off[u + 1] - b);
+    const int64_t t0 = tpre[u];
+    const uint32_t cnt = (uint32_t)(tpre[u + 1] - t0);
+    const uint32_t s = du - cnt;  // first entry above u
+    for (uint32_t i = lane; i < cnt; i += 64) {
+      const uint32_t k = s + i;
+      const int32_t v = nbr[b + k];
+      const uint32_t dv = (uint32_t)(off[v + 1] - off[v]);
+      float x[NI];
+      task_features(du, dv, du - k - 1, x);
+      float* o = feat + (t0 + i) * NI;
+      for (int q = 0; q < NI; ++q) o[q] = x[q];
+    }
+  }
+}
+
+__global__ void k_task_counts(int64_t n, const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                              int64_t* __restrict__ ntask) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    int64_t lo = off[u], hi = off[u + 1];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (nbr[mid] <= (int32_t)u) lo = mid + 1; else hi = mid;
+    }
+    ntask[u] = off[u + 1] - lo;
+  }
+}
+
+// ---------------------------------------------------------------- MLP kernels
+
+__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ gw, const float* __restrict__ x, int64_t m,
+                              float* __restrict__ y) {
+  __shared__ float w[NP];
+  load_weights(gw, w);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += stride) {
+    float xi[NI];
+    for (int i = 0; i < NI; ++i) xi[i] = x[s * NI + i];
+    y[s] = mlp_forward(w, xi);
+  }
+}
+
+// Sample index of position p in a minibatch: identity, or a counter-based
+// hash (SplitMix64 finaliser) of (seed, step, p) for sampling with replacement.
+__device__ __forceinline__ int64_t sample_index(uint64_t seed, uint64_t step, int64_t p, int64_t m, bool hashed) {
+  if (!hashed) return p;
+  uint64_t z = seed + step * 0x9E3779B97F4A7C15ull + (uint64_t)p * 0xD1B54A32D192ED03ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (int64_t)((unsigned __int128)z * (uint64_t)m >> 64);
+}
+
+// Gradient of L = (1/count) sum_s (model(x_s) - t_s)^2 over `count` samples
+// (positions p0 .. p0+count of the sample stream), accumulated into g[NP]
+// with one atomic add per parameter per block; loss sum into loss[0].
+// Backpropagation: dy = 2(y - t)/count; dW3 = dy h2; dh2 = dy W3 [h2 > 0];
+// dW2 = dh2 h1^T; dh1 = W2^T dh2 [h1 > 0]; dW1 = dh1 x^T; biases likewise.
+constexpr int GB = 128;  // samples per block
+__global__ void __launch_bounds__(GB) k_mlp_grad(const float* __restrict__ gw, const float* __restrict__ x,
+                                                 const float* __restrict__ t, int64_t m, int64_t p0, int64_t count,
+                                                 uint64_t seed, uint64_t step, int hashed, float* __restrict__ grad,
+                                                 float* __restrict__ loss) {
+  __shared__ float w[NP];
+  __shared__ float H1[GB][NH + 1], H2[GB][NH + 1], D1[GB][NH + 1], D2[GB][NH + 1];
+  __shared__ float X[GB][NI], G[GB], LS[GB];
+  load_weights(gw, w);
+  const int tid = threadIdx.x;
+  const int64_t p = (int64_t)blockIdx.x * GB + tid;
+  const bool valid = p < count;
+  float xi[NI], h1[NH], h2[NH];
+  float dy = 0.0f;
+  if (valid) {
+    const int64_t s = sample_index(seed, step, p0 + p, m, hashed != 0);
+    for (int i = 0; i < NI; ++i) xi[i] = x[s * NI + i];
+    for (int j = 0; j < NH; ++j) {
+      float a = w[OB1 + j];
+      for (int i = 0; i < NI; ++i) a = fmaf(w[OW1 + j * NI + i], xi[i], a);
+      h1[j] = a > 0.0f ? a : 0.0f;
+    }
+    float y = w[OB3];
+    for (int j = 0; j < NH; ++j) {
+      float a = w[OB2 + j];
+      for (int k = 0; k < NH; ++k) a = fmaf(w[OW2 + j * NH + k], h1[k], a);
+      h2[j] = a > 0.0f ? a : 0.0f;
+      y = fmaf(w[OW3 + j], h2[j], y);
+    }
+    const float e = y - t[s];
+    dy = 2.0f * e / (float)count;
+    LS[tid] = e * e;
+  } else {
+    for (int i = 0; i < NI; ++i) xi[i] = 0.0f;
+    for (int j = 0; j < NH; ++j) h1[j] = h2[j] = 0.0f;
+    LS[tid] = 0.0f;
+  }
+  float d2[NH];
+  for (int j = 0; j < NH; ++j) d2[j] = h2[j] > 0.0f ? dy * w[OW3 + j] : 0.0f;
+  for (int k = 0; k < NH; ++k) {
+    float a = 0.0f;
+    for (int j = 0; j < NH; ++j) a = fmaf(w[OW2 + j * NH + k], d2[j], a);
+    D1[tid][k] = h1[k] > 0.0f ? a : 0.0f;
+    H1[tid][k] = h1[k];
+    H2[tid][k] = h2[k];
+    D2[tid][k] = d2[k];
+  }
+  for (int i = 0; i < NI; ++i) X[tid][i] = xi[i];
+  G[tid] = dy;
+  __syncthreads();
+  // block sums over the samples, one parameter per thread per pass
+  for (int q = tid; q < NP; q += GB) {
+    float acc = 0.0f;
+    if (q < OB1) {
+      const int j = q / NI, i = q % NI;
+      for (int s = 0; s < GB; ++s) acc = fmaf(D1[s][j], X[s][i], acc);
+    } else if (q < OW2) {
+      const int j = q - OB1;
+      for (int s = 0; s < GB; ++s) acc += D1[s][j];
+    } else if (q < OB2) {
+      const int j = (q - OW2) / NH, k = (q - OW2) % NH;
+      for (int s = 0; s < GB; ++s) acc = fmaf(D2[s][j], H1[s][k], acc);
+    } else if (q < OW3) {
+      const int j = q - OB2;
+      for (int s = 0; s < GB; ++s) acc += D2[s][j];
+    } else if (q < OB3) {
+      const int j = q - OW3;
+      for (int s = 0; s < GB; ++s) acc = fmaf(G[s], H2[s][j], acc);
+    } else {
+      for (int s = 0; s < GB; ++s) acc += G[s];
+    }
+    atomicAdd(&grad[q], acc);
+  }
+  if (tid == 0) {
+    float l = 0.0f;
+    for (int s = 0; s < GB; ++s) l += LS[s];
+    atomicAdd(loss, l);
+  }
+}
+
+__global__ void k_adam(float* __restrict__ w, float* __restrict__ m1, float* __restrict__ m2,
+                       const float* __restrict__ g, float lr, float c1, float c2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= NP) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float gq = g[q];
+  const float a = b1 * m1[q] + (1.0f - b1) * gq;
+  const float b = b2 * m2[q] + (1.0f - b2) * gq * gq;
+  m1[q] = a;
+  m2[q] = b;
+  w[q] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+}
+
+__global__ void k_zero_f32(float* p, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) p[i] = 0.0f;
+}
+
+// ---------------------------------------------------------------- schedule
+
+// Cost bin of every non-split task: 4 bins per octave of the cost
+// (mode 1: d(u)+d(v); mode 2: the model's predicted cycles, whose log2 it
+// outputs). Split tasks get bin 0 (they are skipped by the census queue).
+__global__ void __launch_bounds__(256) k_task_bins(int mode, const float* __restrict__ gw, const int64_t* __restrict__ off,
+                            const uint32_t* __restrict__ packed, const uint64_t* __restrict__ tasks, int64_t ntasks,
+                            uint8_t* __restrict__ bin, unsigned long long* __restrict__ counts) {
+  __shared__ float w[NP];
+  __shared__ unsigned int cnt[SCHED_BINS];
+  if (mode == 2) load_weights(gw, w);
+  for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntasks; t += stride) {
+    const uint64_t tk = tasks[t];
+    int b = 0;
+    if (!(tk & HUB_BIT)) {
+      const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu, k = (uint32_t)tk;
+      const int64_t au = off[u];
+      const uint32_t du = (uint32_t)(off[u + 1] - au);
+      const uint32_t v = packed[au + k] >> 2;
+      const uint32_t dv = (uint32_t)(off[v + 1] - off[v]);
+      float c;
+      if (mode == 2) {
+        float x[NI];
+        task_features(du, dv, du - k - 1, x);
+        c = mlp_forward(w, x);
+      } else {
+        c = log2f((float)du + (float)dv);
+      }
+      b = (int)floorf(c * 4.0f);
+      b = b < 0 ? 0 : (b >= SCHED_BINS ? SCHED_BINS - 1 : b);
+    }
+    bin[t] = (uint8_t)b;
+    atomicAdd(&cnt[b], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x)
+    if (cnt[b]) atomicAdd(&counts[b], (unsigned long long)cnt[b]);
+}
+
+// Bin starts for descending bin order (costliest first).
+__global__ void k_bin_starts(unsigned long long* counts) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long run = 0;
+  for (int b = SCHED_BINS - 1; b >= 0; --b) {
+    const unsigned long long c = counts[b];
+    counts[b] = run;
+    run += c;
+  }
+}
+
+// Scatter task ids into their bins: one global reservation per (block, bin),
+// then block-local slots.
+__global__ void k_bin_scatter(const uint8_t* __restrict__ bin, int64_t ntasks, unsigned long long* __restrict__ cursor,
+                              int64_t* __restrict__ order) {
+  __shared__ unsigned int cnt[SCHED_BINS];
+  __shared__ unsigned long long base[SCHED_BINS];
+  const int64_t per_block = (int64_t)blockDim.x * 16;
+  for (int64_t t0 = (int64_t)blockIdx.x * per_block; t0 < ntasks; t0 += (int64_t)gridDim.x * per_block) {
+    for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) cnt[b] = 0;
+    __syncthreads();
+    const int64_t t1 = min(t0 + per_block, ntasks);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) atomicAdd(&cnt[bin[t]], 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) {
+      base[b] = cnt[b] ? atomicAdd(&cursor[b], (unsigned long long)cnt[b]) : 0ull;
+      cnt[b] = 0;
+    }
+    __syncthreads();
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+      const int b = bin[t];
+      const unsigned int r = atomicAdd(&cnt[b], 1u);
+      order[base[b] + r] = t;
+    }
+    __syncthreads();
+  }
+}
+
+static int grid_of(int64_t work, int threads, int cap) {
+  int64_t g = (work + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+int build_order(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* packed,
+                const uint64_t* tasks, int64_t ntasks, int64_t* order, Scratch& scratch, hipStream_t s) {
+  (void)n;
+  if (ntasks <= 0) return TRIAD_OK;
+  uint8_t* bin = nullptr;
+  unsigned long long* counts = nullptr;
+  ALLOC(bin, ntasks);
+  ALLOC(counts, SCHED_BINS);
+  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, (float*)counts, (int64_t)(2 * SCHED_BINS));
+  hipLaunchKernelGGL(k_task_bins, dim3(grid_of(ntasks, 256, 16384)), dim3(256), 0, s, mode, model, off, packed, tasks,
+                     ntasks, bin, counts);
+  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, s, counts);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(grid_of(ntasks, 256 * 16, 8192)), dim3(256), 0, s, bin, ntasks, counts, order);
+  HIPCHK(hipGetLastError());
+  return TRIAD_OK;
+}
+
+}  // namespace triad
+
+using namespace triad;
+
+extern "C" {
+
+int triad_task_features(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, void* stream, float* d_feat,
+                        int64_t* ntasks_out) {
+  hipStream_t s = (hipStream_t)stream;
+  if (n < 0 || n >= ((int64_t)1 << 30) || nnz < 0) return fail(TRIAD_EINVAL, "bad sizes");
+  if (!off || (nnz > 0 && !nbr)) return fail(TRIAD_EINVAL, "NULL pointer argument");
+  Scratch scratch(s);
+  int64_t* ntask = nullptr;
+  int64_t* tpre = nullptr;
+  ALLOC(ntask, n + 1);
+  ALLOC(tpre, n + 1);
+  int64_t total = 0;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_task_counts, dim3(grid_of(n, 256, 65535)), dim3(256), 0, s, n, off, nbr, ntask);
+    // exclusive prefix of the per-row task counts (host side: this entry point
+    // prepares training data and is not on the census path)
+    std::vector<int64_t> h((size_t)n + 1);
+    HIPCHK(hipMemcpyAsync(h.data(), ntask, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t run = 0;
+    for (int64_t u = 0; u < n; ++u) {
+      const int64_t c = h[u];
+      h[u] = run;
+      run += c;
+    }
+    h[n] = run;
+    total = run;
+    HIPCHK(hipMemcpyAsync(tpre, h.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    if (d_feat && total > 0)
+      hipLaunchKernelGGL(k_features_csr, dim3(grid_of(n * 64, 256, 32768)), dim3(256), 0, s, n, off, nbr, tpre, d_feat);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (ntasks_out) *ntasks_out = total;
+  return TRIAD_OK;
+}
+
+int triad_mlp_forward(const float* d_w, const float* d_x, int64_t m, float* d_y, void* stream) {
+  if (!d_w || (m > 0 && (!d_x || !d_y)) || m < 0) return fail(TRIAD_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  if (m > 0) hipLaunchKernelGGL(k_mlp_forward, dim3(grid_of(m, 256, 65535)), dim3(256), 0, s, d_w, d_x, m, d_y);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return TRIAD_OK;
+}
+
+int triad_mlp_loss_grad(const float* d_w, const float* d_x, const float* d_t, int64_t m, float* d_grad, float* d_loss,
+                        void* stream) {
+  if (!d_w || !d_grad || !d_loss || m <= 0 || !d_x || !d_t) return fail(TRIAD_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid_of(NP, 256, 64)), dim3(256), 0, s, d_grad, (int64_t)NP);
+  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, d_loss, (int64_t)1);
+  hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)((m + GB - 1) / GB)), dim3(GB), 0, s, d_w, d_x, d_t, m, (int64_t)0, m,
+                     (uint64_t)0, (uint64_t)0, 0, d_grad, d_loss);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  // the kernel accumulates the squared-error sum; report the mean
+  float l = 0;
+  HIPCHK(hipMemcpy(&l, d_loss, sizeof(float), hipMemcpyDeviceToHost));
+  l /= (float)m;
+  HIPCHK(hipMemcpy(d_loss, &l, sizeof(float), hipMemcpyHostToDevice));
+  return TRIAD_OK;
+}
+
+int triad_mlp_adam(float* d_w, float* d_m, float* d_v, const float* d_grad, int32_t t, float lr, void* stream) {
+  if (!d_w || !d_m || !d_v || !d_grad || t < 1) return fail(TRIAD_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+  hipLaunchKernelGGL(k_adam, dim3((NP + 255) / 256), dim3(256), 0, s, d_w, d_m, d_v, d_grad, lr, c1, c2);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return TRIAD_OK;
+}
+
+int triad_mlp_train(float* d_w, const float* d_x, const float* d_t, int64_t m, int32_t epochs, int32_t batch, float lr,
+                    uint64_t seed, void* stream, float* d_loss_hist) {
+  if (!d_w || !d_x || !d_t || m <= 0 || epochs < 1 || batch < 1) return fail(TRIAD_EINVAL, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  Scratch scratch(s);
+  float *m1 = nullptr, *m2 = nullptr, *g = nullptr, *loss = nullptr;
+  ALLOC(m1, NP);
+  ALLOC(m2, NP);
+  ALLOC(g, NP);
+  ALLOC(loss, epochs);
+  hipLaunchKernelGGL(k_zero_f32, dim3(8), dim3(256), 0, s, m1, (int64_t)NP);
+  hipLaunchKernelGGL(k_zero_f32, dim3(8), dim3(256), 0, s, m2, (int64_t)NP);
+  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, loss, (int64_t)epochs);
+  const int64_t steps = (m + batch - 1) / batch;
+  int32_t t = 0;
+  for (int e = 0; e < epochs; ++e) {
+    for (int64_t st = 0; st < steps; ++st) {
+      ++t;
+      hipLaunchKernelGGL(k_zero_f32, dim3(8), dim3(256), 0, s, g, (int64_t)NP);
+      // minibatch of `batch` samples drawn with replacement by a counter-based hash
+      hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)((batch + GB - 1) / GB)), dim3(GB), 0, s, (const float*)d_w, d_x,
+                         d_t, m, (int64_t)0, (int64_t)batch, seed, (uint64_t)t, 1, g, loss + e);
+      const float c1 = 1.0f - powf(0.9f, (float)t), c2 = 1.0f - powf(0.999f, (float)t);
+      hipLaunchKernelGGL(k_adam, dim3((NP + 255) / 256), dim3(256), 0, s, d_w, m1, m2, (const float*)g, lr, c1, c2);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  if (d_loss_hist) {
+    std::vector<float> h((size_t)epochs);
+    HIPCHK(hipMemcpyAsync(h.data(), loss, sizeof(float) * epochs, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (auto& x : h) x /= (float)(steps * batch);
+    HIPCHK(hipMemcpyAsync(d_loss_hist, h.data(), sizeof(float) * epochs, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return TRIAD_OK;
+}
+
+}  // extern "C"

@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "triad.h"
 
@@ -46,5 +48,49 @@ struct DeviceInfo {
   std::string name;
 };
 int device_info(DeviceInfo* out);
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      return fail(TRIAD_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+// Stream-ordered scratch memory, released (in stream order) on destruction.
+struct Scratch {
+  hipStream_t s;
+  std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t st) : s(st) {}
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+  template <class T>
+  hipError_t get(T** p, int64_t count) {
+    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMallocAsync((void**)p, bytes, s);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+};
+
+#define ALLOC(ptr, count)                                                                        \
+  do {                                                                                           \
+    hipError_t e_ = scratch.get(&(ptr), (count));                                                \
+    if (e_ != hipSuccess) {                                                                      \
+      (void)hipGetLastError();                                                                   \
+      return fail(TRIAD_ENOMEM, std::string("device allocation of ") + #ptr + " failed");       \
+    }                                                                                            \
+  } while (0)
+
+// Task (u, k): u in bits 32..61, k (index of v in the row of u) in bits 0..31;
+// bit 63 marks a task that is split into chunks (merged from the hub list).
+constexpr uint64_t HUB_BIT = 1ull << 63;
+
+// Schedule: a permutation `order` of the task indices, longest-first by a cost
+// key binned into SCHED_BINS bins (counting sort). mode 1 = d(u)+d(v),
+// mode 2 = the learned model's predicted log2 cycles (model = device weights).
+constexpr int SCHED_BINS = 128;
+int build_order(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* packed,
+                const uint64_t* tasks, int64_t ntasks, int64_t* order, Scratch& scratch, hipStream_t s);
 
 }  // namespace triad

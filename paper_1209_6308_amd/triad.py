@@ -50,7 +50,7 @@ class TriadError(RuntimeError):
 class Timing(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_float), ("tasks_ms", ctypes.c_float), ("census_ms", ctypes.c_float),
                 ("finalize_ms", ctypes.c_float), ("tasks", ctypes.c_int64), ("hub_tasks", ctypes.c_int64),
-                ("items", ctypes.c_int64)]
+                ("items", ctypes.c_int64), ("waves", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -60,7 +60,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("validate", ctypes.c_int32), ("hub_threshold", ctypes.c_int64),
                 ("chunk", ctypes.c_int64), ("model", ctypes.c_void_p), ("task_cycles", ctypes.c_void_p),
                 ("timing", ctypes.POINTER(Timing)), ("waves_per_group", ctypes.c_int32),
-                ("grid_groups", ctypes.c_int32)]
+                ("grid_groups", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
+                ("wave_span", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -133,7 +134,7 @@ def _stream(stream=None):
 
 
 def make_opts(schedule="plain", validate=0, hub_threshold=0, chunk=0, model=None, task_cycles=None,
-              waves_per_group=0, grid_groups=0, timing=None):
+              waves_per_group=0, grid_groups=0, timing=None, wave_span=None, kernel_variant=0):
     o = Opts()
     o.schedule = SCHED[schedule] if isinstance(schedule, str) else int(schedule)
     o.validate = validate
@@ -143,6 +144,8 @@ def make_opts(schedule="plain", validate=0, hub_threshold=0, chunk=0, model=None
     o.task_cycles = task_cycles.data_ptr() if task_cycles is not None else None
     o.waves_per_group = waves_per_group
     o.grid_groups = grid_groups
+    o.kernel_variant = kernel_variant
+    o.wave_span = wave_span.data_ptr() if wave_span is not None else None
     if timing is not None:
         o.timing = ctypes.pointer(timing)
     return o
@@ -194,3 +197,67 @@ def to_device(g, device="cuda"):
     import torch
     return (torch.from_numpy(g.offsets).to(device), torch.from_numpy(g.nbrs).to(device),
             torch.from_numpy(g.flags).to(device))
+
+
+# ------------------------------------------------------------------ batches
+
+def batch_to_device(B, device="cuda"):
+    """Copy a graphs.BatchCSR to device tensors: (vbase, offsets, nbrs, flags)."""
+    import torch
+    return tuple(torch.from_numpy(a).to(device) for a in (B.vbase, B.offsets, B.nbrs, B.flags))
+
+
+class BatchPlan:
+    """A captured hipGraph of the batched census for one concatenated CSR."""
+
+    def __init__(self, G, nv, nnz, d_vbase, d_off, d_nbr, d_flg, d_out=None, stream=None, **kw):
+        import torch
+        self.G = G
+        self.d_out = d_out if d_out is not None else torch.empty((G, 16), dtype=torch.int64, device=d_off.device)
+        self._keep = (d_vbase, d_off, d_nbr, d_flg)
+        o = make_opts(**kw)
+        h = ctypes.c_void_p()
+        _check(lib().triad_batch_plan_create(G, nv, nnz, _tp(d_vbase), _tp(d_off), _tp(d_nbr), _tp(d_flg),
+                                             _tp(self.d_out), ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(lib().triad_batch_plan_launch(self.h, _stream(stream)))
+
+    def status(self):
+        return _check(lib().triad_batch_plan_status(self.h))
+
+    def result(self):
+        """Per-graph censuses as a [G][16] list of Python ints (waits for the launch)."""
+        self.status()
+        return [[int(x) & ((1 << 64) - 1) for x in row] for row in self.d_out.cpu().tolist()]
+
+    def close(self):
+        if self.h:
+            lib().triad_batch_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def triad_census_batch(G, nv, nnz, d_vbase, d_off, d_nbr, d_flg, stream=None, **kw):
+    """One-shot batched census; returns a [G][16] list of Python ints."""
+    import torch
+    out = torch.empty((G, 16), dtype=torch.int64, device=d_off.device)
+    o = make_opts(**kw)
+    _check(lib().triad_census_batch(G, nv, nnz, _tp(d_vbase), _tp(d_off), _tp(d_nbr), _tp(d_flg), ctypes.byref(o),
+                                    _stream(stream), _tp(out)))
+    return [[int(x) & ((1 << 64) - 1) for x in row] for row in out.cpu().tolist()]
+
+
+def batch_autotune(G, nv, nnz, d_vbase, d_off, d_nbr, d_flg, cache_path=None, stream=None):
+    """Fastest launch shape for this batch (dict of triad_opts fields)."""
+    o = Opts()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().triad_batch_autotune(G, nv, nnz, _tp(d_vbase), _tp(d_off), _tp(d_nbr), _tp(d_flg), _stream(stream),
+                                      cp, ctypes.byref(o)))
+    return {"kernel_variant": o.kernel_variant, "waves_per_group": o.waves_per_group, "grid_groups": o.grid_groups}

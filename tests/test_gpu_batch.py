@@ -1,0 +1,119 @@
+"""Batched census (one captured hipGraph over many graphs) against the oracle,
+graph by graph, bit-exact."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_6308_amd import graphs, triad
+
+from _helpers import GOLDEN, random_digraph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no HIP device")
+    return t
+
+
+def concat(members):
+    """BatchCSR from a list of graphs.CSR (graph-local ids)."""
+    vb = [0]
+    offs, nbs, fls = [np.zeros(1, np.int64)], [], []
+    e0 = 0
+    for g in members:
+        vb.append(vb[-1] + g.n)
+        offs.append(g.offsets[1:] + e0)
+        nbs.append(g.nbrs)
+        fls.append(g.flag_array())
+        e0 += g.nnz
+    f = np.concatenate(fls) if fls else np.zeros(0, np.uint8)
+    j = np.arange(f.size)
+    packed = np.zeros((f.size + 3) // 4, np.uint8)
+    np.bitwise_or.at(packed, j >> 2, (f << (2 * (j & 3))).astype(np.uint8))
+    return graphs.BatchCSR(len(members), np.array(vb, np.int64), np.concatenate(offs).astype(np.int64),
+                           np.concatenate(nbs).astype(np.int32) if nbs else np.zeros(0, np.int32), packed,
+                           np.zeros((len(members), 6)))
+
+
+def test_small_ensemble(torch):
+    B = graphs.null_ensemble(G=48, seed=5, nmin=64, nmax=700, dmin=4, dmax=20)
+    d = triad.batch_to_device(B)
+    got = triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d)
+    for g in range(B.G):
+        assert got[g] == oracle.census(B.graph(g)), g
+
+
+def test_degenerate_members(torch):
+    rng_graphs = [graphs.build_csr(0, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+                  graphs.build_csr(1, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+                  graphs.from_arcs(2, [(0, 1), (1, 0)]),
+                  graphs.build_csr(9, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+                  graphs.from_arcs(3, [(0, 1), (1, 2), (2, 0)])]
+    for k, (n, dens, rec) in enumerate([(40, 0.3, 0.3), (65, 0.1, 1.0), (130, 0.05, 0.0)]):
+        s, t = random_digraph(n, dens, rec, 100 + k)
+        rng_graphs.append(graphs.build_csr(n, s, t))
+    B = concat(rng_graphs)
+    d = triad.batch_to_device(B)
+    got = triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d)
+    for g, m in enumerate(rng_graphs):
+        assert got[g] == oracle.census(m), g
+
+
+def test_graph_replays(torch):
+    B = graphs.null_ensemble(G=32, seed=6, nmin=64, nmax=400, dmin=4, dmax=16)
+    want = [oracle.census(B.graph(g)) for g in range(B.G)]
+    d = triad.batch_to_device(B)
+    plan = triad.BatchPlan(B.G, int(B.vbase[-1]), B.nnz, *d)
+    for rep in range(4):
+        plan.launch()
+        assert plan.result() == want, rep
+        # eager work on the same stream between replays
+        x = torch.arange(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert int(x) == (1 << 20) * ((1 << 20) - 1) // 2
+    plan.close()
+
+
+def test_batch_validation_error(torch):
+    B = graphs.null_ensemble(G=4, seed=7, nmin=64, nmax=100, dmin=4, dmax=8)
+    nb = B.nbrs.copy()
+    nb[5] = 100000  # out of its graph's range
+    d = list(triad.batch_to_device(B))
+    d[2] = torch.from_numpy(nb).cuda()
+    with pytest.raises(triad.TriadError) as e:
+        triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d)
+    assert e.value.status == triad.ERANGE
+
+
+def test_autotune_and_cache(torch, tmp_path):
+    B = graphs.null_ensemble(G=64, seed=8, nmin=64, nmax=900, dmin=4, dmax=24)
+    want = [oracle.census(B.graph(g)) for g in range(B.G)]
+    d = triad.batch_to_device(B)
+    cache = str(tmp_path / "tune.jsonl")
+    best = triad.batch_autotune(B.G, int(B.vbase[-1]), B.nnz, *d, cache_path=cache)
+    assert best["kernel_variant"] > 0 and best["waves_per_group"] in (1, 2)
+    again = triad.batch_autotune(B.G, int(B.vbase[-1]), B.nnz, *d, cache_path=cache)
+    assert again == best
+    assert len(open(cache).read().strip().splitlines()) == 1
+    assert triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d, **best) == want
+
+
+def test_full_ensemble_golden(torch):
+    path = os.path.join(GOLDEN, "census_nullens.json")
+    if not os.path.exists(path):
+        pytest.skip("golden not generated")
+    rec = json.load(open(path))
+    p = rec["params"]
+    B = graphs.null_ensemble(G=p["G"], seed=p["seed"], nmin=p["nmin"], nmax=p["nmax"], dmin=p["dmin"],
+                             dmax=p["dmax"], rmax=p["rmax"], swap_factor=p["swap_factor"])
+    assert B.content_hash() == rec["content_hash"]
+    d = triad.batch_to_device(B)
+    got = triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d)
+    assert [[str(x) for x in row] for row in got] == rec["census"]

@@ -157,7 +157,7 @@ def _golden(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("name", ["rmat20"])
+@pytest.mark.parametrize("name", ["rmat20", "cl22", "rmat24"])
 def test_full_size_golden(torch_cuda, name):
     rec = _golden(name)
     g = graphs.workload(name)
