@@ -33,8 +33,8 @@ __device__ __forceinline__ void task_features(uint32_t du, uint32_t dv, uint32_t
   x[5] = log2f(1.0f + (float)above);
 }
 
-// y = W3 . relu(W2 relu(W1 x + b1) + b2) + b3, weights w in LDS.
-__device__ __forceinline__ float mlp_forward(const float* w, const float x[NI]) {
+// y = W3 . relu(W2 relu(W1 x + b1) + b2) + b3.
+__device__ __forceinline__ float mlp_forward(const float* __restrict__ w, const float x[NI]) {
   float h1[NH];
 #pragma unroll
   for (int j = 0; j < NH; ++j) {
@@ -102,13 +102,11 @@ __global__ void k_task_counts(int64_t n, const int64_t* __restrict__ off, const 
 
 __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ gw, const float* __restrict__ x, int64_t m,
                               float* __restrict__ y) {
-  __shared__ float w[NP];
-  load_weights(gw, w);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += stride) {
     float xi[NI];
     for (int i = 0; i < NI; ++i) xi[i] = x[s * NI + i];
-    y[s] = mlp_forward(w, xi);
+    y[s] = mlp_forward(gw, xi);
   }
 }
 
@@ -231,12 +229,12 @@ __global__ void k_zero_f32(float* p, int64_t m) {
 // Cost bin of every non-split task: 4 bins per octave of the cost
 // (mode 1: d(u)+d(v); mode 2: the model's predicted cycles, whose log2 it
 // outputs). Split tasks get bin 0 (they are skipped by the census queue).
+// The weights are read from global memory at wave-uniform addresses, so they
+// arrive through the scalar cache and each multiply-add takes one VALU op.
 __global__ void __launch_bounds__(256) k_task_bins(int mode, const float* __restrict__ gw, const int64_t* __restrict__ off,
                             const uint32_t* __restrict__ packed, const uint64_t* __restrict__ tasks, int64_t ntasks,
                             uint8_t* __restrict__ bin, unsigned long long* __restrict__ counts) {
-  __shared__ float w[NP];
   __shared__ unsigned int cnt[SCHED_BINS];
-  if (mode == 2) load_weights(gw, w);
   for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) cnt[b] = 0;
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -253,7 +251,7 @@ __global__ void __launch_bounds__(256) k_task_bins(int mode, const float* __rest
       if (mode == 2) {
         float x[NI];
         task_features(du, dv, du - k - 1, x);
-        c = mlp_forward(w, x);
+        c = mlp_forward(gw, x);
       } else {
         c = log2f((float)du + (float)dv);
       }
