@@ -293,6 +293,27 @@ struct Batch {
   int32_t dyad;
 };
 
+// Adds the batch's dyadic terms n - d(u) - d(v) (Fig. 5 step 2.1.3; the
+// intersection part is counted by the merge) to counter 012 or 102 by the u-v
+// dyad: one wave reduction and one atomic per counter when the whole batch
+// belongs to one graph, per-lane atomics otherwise (batched census only).
+template <bool BAT>
+__device__ void add_dyads(const CensusArgs& g, int lane, const Batch& bt) {
+  const uint64_t dv = (uint64_t)(int64_t)bt.dyad;
+  const bool mut = (bt.vf & 3u) == 3u;
+  const uint32_t g0 = bcast32(bt.gid, 0);
+  if (!BAT || __ballot(bt.dyad != 0 && bt.gid != g0) == 0) {
+    const uint64_t sa = wave_sum64(mut ? 0 : dv), sm = wave_sum64(mut ? dv : 0);
+    unsigned long long* tgt = BAT ? g.gout + 16 * (uint64_t)g0 : g.acc;
+    if (lane == 0) {
+      if (sa) atomicAdd(&tgt[1], (unsigned long long)sa);
+      if (sm) atomicAdd(&tgt[2], (unsigned long long)sm);
+    }
+  } else if (bt.dyad != 0) {
+    atomicAdd(&g.gout[16 * (uint64_t)bt.gid + (mut ? 2 : 1)], (unsigned long long)dv);
+  }
+}
+
 // Claims the next batch: hub chunks first (phase 0), then whole tasks
 // (phase 1). Returns false when both queues are drained.
 template <bool BAT>
@@ -373,6 +394,7 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
         }
       }
     }
+    add_dyads<BAT>(g, lane, bt);
     return true;
   }
 }
@@ -382,13 +404,13 @@ struct Item {
   const uint32_t* A;
   const uint32_t* B;
   uint32_t la, lb, uq, vq, f, kind, gid;
-  int32_t dyad;
+  uint64_t slice;  // class table slice of f = f_uv
   int64_t tid;
 };
 
-__device__ __forceinline__ void item_of(const Batch& bt, int it, const uint32_t* packed, Item& x) {
-  x.A = packed + (int64_t)bcast64((uint64_t)bt.aoff, it);
-  x.B = packed + (int64_t)bcast64((uint64_t)bt.boff, it);
+__device__ __forceinline__ void item_of(const Batch& bt, int it, const CensusArgs& g, Item& x) {
+  x.A = g.packed + (int64_t)bcast64((uint64_t)bt.aoff, it);
+  x.B = g.packed + (int64_t)bcast64((uint64_t)bt.boff, it);
   x.la = bcast32(bt.la, it);
   x.lb = bcast32(bt.lb, it);
   const uint32_t uf = bcast32(bt.uf, it), vf = bcast32(bt.vf, it);
@@ -396,7 +418,9 @@ __device__ __forceinline__ void item_of(const Batch& bt, int it, const uint32_t*
   x.vq = vf | 3u;
   x.f = vf & 3u;
   x.kind = uf >> 30;
-  x.dyad = (int32_t)bcast32((uint32_t)bt.dyad, it);
+  // a select between kernel arguments: no load is queued behind the window
+  // prefetch, whose completion the merge must not wait for
+  x.slice = x.f == 3u ? g.cls.s[3] : (x.f == 2u ? g.cls.s[2] : g.cls.s[1]);
   x.gid = bcast32(bt.gid, it);
   x.tid = (int64_t)bcast64((uint64_t)bt.tid, it);
 }
@@ -489,10 +513,9 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   wave_lds_sync();
   const uint32_t col = (uint32_t)(lane & (C - 1));
   // counters 1 (012) and 2 (102) hold each lane's count of ids found in both
-  // lists, by the task's u-v dyad; the rest of those two classes is the
-  // wave-uniform n - d(u) - d(v) part
-  uint64_t dy_asym = 0, dy_mut = 0;
-  uint64_t steps = 0;  // bound on any counter's increments since the last flush
+  // lists, by the task's u-v dyad; the rest of those two classes, n - d(u) -
+  // d(v) per task, is added when the batch is claimed
+  uint32_t steps = 0;  // bound on any counter's increments since the last flush
 
   // The pipeline starts on an empty item: its round is a no-op that is
   // immediately "done", so the first real item is claimed by the same code
@@ -508,7 +531,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   cur.f = 1;
   cur.kind = 0;
   cur.gid = 0;
-  cur.dyad = 0;
+  cur.slice = 0;
   cur.tid = 0;
   uint32_t wg = 0xFFFFFFFFu;  // graph whose counters the wavefront holds (batched)
   uint32_t ia = 0, ib = 0;  // position of the current round in the item
@@ -553,7 +576,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
       // skip empty items (hub tasks in the task queue)
       while (nit < bt.cnt && bcast32(bt.la, nit) + bcast32(bt.lb, nit) == 0) ++nit;
       if (nit < bt.cnt) {
-        item_of(bt, nit, g.packed, nxt);
+        item_of(bt, nit, g, nxt);
         it = nit;
       } else {
         // batch exhausted: claim the next one (the current item is already in
@@ -565,7 +588,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
           while (k0 < bt.cnt && bcast32(bt.la, k0) + bcast32(bt.lb, k0) == 0) ++k0;
           if (k0 < bt.cnt) {
             it = k0;
-            item_of(bt, k0, g.packed, nxt);
+            item_of(bt, k0, g, nxt);
             break;
           }
         }
@@ -580,29 +603,21 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
     if (BAT && cur.gid != wg && cur.la + cur.lb > 0) {
       if (wg != 0xFFFFFFFFu) {
         flush_wave(L, lane, g.gout + 16 * (uint64_t)wg);
-        if (lane == 0) {
-          atomicAdd(&g.gout[16 * (uint64_t)wg + 1], (unsigned long long)dy_asym);
-          atomicAdd(&g.gout[16 * (uint64_t)wg + 2], (unsigned long long)dy_mut);
-        }
-        dy_asym = dy_mut = 0;
         steps = 0;
       }
       wg = cur.gid;
     }
-    item_inter += merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, g.cls.s[cur.f], col, lane);
+    item_inter += merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
     steps += (na + nb) / (HH ? 16 : 32) + 4;
     if (item_done) {
       atomicAdd(&L.hist[(cur.f == 3 ? 2 : 1) * C + col], item_inter);
       item_inter = 0;
-      if (cur.kind) {
-        if (cur.f == 3) dy_mut += (uint64_t)(int64_t)cur.dyad; else dy_asym += (uint64_t)(int64_t)cur.dyad;
-      }
       if constexpr (CYC) {
         const uint64_t t_end = __builtin_amdgcn_s_memtime();
         if (lane == 0 && cur.kind == 2) g.cycles[cur.tid] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
         t_start = t_end;
       }
-      if (steps > (1ull << 30)) {
+      if (steps > (1u << 30)) {
         flush_wave(L, lane, BAT ? g.gout + 16 * (uint64_t)wg : g.acc);
         steps = 0;
       }
@@ -618,13 +633,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   unsigned long long* tgt = g.acc;
   if (BAT) tgt = wg != 0xFFFFFFFFu ? g.gout + 16 * (uint64_t)wg : nullptr;
   if (tgt) flush_wave(L, lane, tgt);
-  if (lane == 0) {
-    if (tgt) {
-      atomicAdd(&tgt[1], (unsigned long long)dy_asym);
-      atomicAdd(&tgt[2], (unsigned long long)dy_mut);
-    }
-    if (g.wave_span) g.wave_span[2 * wave_id + 1] = __builtin_amdgcn_s_memrealtime();
-  }
+  if (lane == 0 && g.wave_span) g.wave_span[2 * wave_id + 1] = __builtin_amdgcn_s_memrealtime();
 }
 
 __global__ void k_finalize(const unsigned long long* __restrict__ acc, uint64_t clo, uint64_t chi,
