@@ -43,6 +43,10 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t x, int lane) {
   uint32_t lo = bcast32((uint32_t)x, lane), hi = bcast32((uint32_t)(x >> 32), lane);
   return ((uint64_t)hi << 32) | lo;
 }
+// Marks a wave-uniform value as such for the compiler, which otherwise keeps
+// loop state that passes through divergent code in vector registers.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
@@ -329,7 +333,7 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
       if (phase == 0) { phase = 1; continue; }
       return false;
     }
-    bt.cnt = (int)min((int64_t)BATCH, limit - (int64_t)base);
+    bt.cnt = (int)uni((uint32_t)min((int64_t)BATCH, limit - (int64_t)base));
     bt.la = bt.lb = bt.uf = bt.vf = bt.gid = 0;
     bt.dyad = 0;
     bt.aoff = bt.boff = bt.tid = 0;
@@ -437,10 +441,27 @@ __device__ __forceinline__ void load_round(const uint32_t* A, uint32_t na_ld, co
     if ((uint32_t)(j * 64) < nb_ld) rb[j] = B[j * 64 + lane];
 }
 
+// Number of entries of the sorted window x[0, n) with key <= bound, 0 < n <= W:
+// a 64-ary search, one LDS read per lane for the last key of each of 64
+// blocks of W/64 entries, then one per lane in the block holding the boundary.
+template <int W>
+__device__ __forceinline__ uint32_t count_le(const uint32_t* x, uint32_t n, uint32_t bound, int lane) {
+  constexpr uint32_t S = W / 64;
+  const uint32_t l = (uint32_t)lane;
+  const bool in = l * S < n;
+  const uint32_t last = key_of(x[min(l * S + S - 1, n - 1)]);
+  const uint32_t c1 = (uint32_t)__popcll(__ballot(in && last <= bound));  // whole blocks <= bound
+  if (c1 * S >= n) return n;
+  const uint32_t e = c1 * S + l;
+  const bool in2 = l < S && e < n;
+  const uint32_t v = key_of(x[in2 ? e : 0]);
+  return c1 * S + (uint32_t)__popcll(__ballot(in2 && v <= bound));
+}
+
 // Per-lane two-pointer walk of the lane's merge-path range of one round:
 // one distinct w per step, classified in situ from its direction bits
 // (Fig. 5 steps 2.1.4-2.1.4.2, Sec. 6). Returns the number of ids found in
-// both lists (entries consumed minus steps taken).
+// both lists.
 template <int W, bool HH>
 __device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
                                                 uint32_t vq, uint64_t slice, uint32_t col, int lane) {
@@ -455,27 +476,33 @@ __device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, 
   // an id shared by A[i-1] and B[k] was consumed with A[i-1] by a lane before
   if (i > 0 && k < nb && key_of(L.a[i - 1]) == key_of(L.b[k])) ++k;
   const uint32_t start = i + k;
-  uint32_t a = L.a[i], b = L.b[k];
-  uint32_t steps = 0;
-  while (i + k < d1) {
+  uint32_t pos = start, steps = 0;
+  uint32_t* const hcol = L.hist + col;
+  // The lane predicates are kept as wavefront masks so that their logic runs
+  // on the scalar unit; the vector unit only compares, selects and adds.
+  while (pos < d1) {
+    const uint32_t a = L.a[i], b = L.b[k];
     const uint32_t ea = a | 3u, eb = b | 3u;
-    const bool tA = ea <= eb, tB = eb <= ea;
-    const uint32_t w = ea < eb ? ea : eb;
-    // canonical selection (Fig. 5 step 2.1.4): v < w, or u < w < v with w not in N(u)
-    const bool counted = (w > vq) | ((w > uq) & !tA);
-    // 4-bit index fa | fb << 2 of the flags of w in N(u) and N(v); 0 when this
-    // edge does not own the triad
-    uint32_t idx = (tA ? (a & 3u) : 0u) | (tB ? ((b & 3u) << 2) : 0u);
-    idx = counted ? idx : 0u;
-    const uint32_t cls = (uint32_t)(slice >> (idx << 2)) & 15u;
-    atomicAdd(&L.hist[cls * WaveLds<W, HH>::COLS + col], 1u);
+    const bool ta = ea <= eb, tb = eb <= ea;  // w is in N(u), in N(v)
+    const uint64_t tA = __builtin_amdgcn_ballot_w64(ta), tB = __builtin_amdgcn_ballot_w64(tb);
+    // canonical selection (Fig. 5 step 2.1.4): a w taken from N(u), alone or
+    // shared, is counted iff v < w; a w found in N(v) only iff u < w
+    const uint64_t mA = tA & __builtin_amdgcn_ballot_w64(ea > vq);
+    const uint64_t mB = (tB & mA) | (__builtin_amdgcn_ballot_w64(eb > uq) & ~tA);
+    // nibble shift 4 * (fa | fb << 2) of the class table, with the flag of a
+    // list that does not hold w, or of an uncounted w, taken as 0
+    const uint32_t fa = __builtin_amdgcn_inverse_ballot_w64(mA) ? a & 3u : 0u;
+    const uint32_t sb = __builtin_amdgcn_inverse_ballot_w64(mB) ? b : 0u;
+    const uint32_t sh = (((sb << 2) | fa) << 2) & 63u;  // the id bits of b shift out
+    const uint32_t cls = (uint32_t)(slice >> sh) & 15u;
+    atomicAdd(hcol + cls * WaveLds<W, HH>::COLS, 1u);
+    i += (uint32_t)ta;
+    k += (uint32_t)tb;
     ++steps;
-    i += (uint32_t)tA;
-    k += (uint32_t)tB;
-    a = L.a[i];
-    b = L.b[k];
+    pos = i + k;
   }
-  return (i + k - start) - steps;
+  // entries consumed minus distinct ids: the ids found in both lists
+  return (pos - start) - steps;
 }
 
 template <int W, bool HH>
@@ -541,25 +568,25 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   uint32_t na_ld = 0, nb_ld = 0;
 
   for (;;) {
-    // ---- stage the loaded round in LDS
+    // ---- stage the loaded round in LDS (register slots past the window hold
+    // stale values; the walk stops at the sentinels and never reads them)
 #pragma unroll
     for (int j = 0; j < W / 64; ++j) {
       const uint32_t k = (uint32_t)(j * 64 + lane);
-      if ((uint32_t)(j * 64) < na_ld) L.a[k] = k < na_ld ? ra[j] : KEY_INF;
-      if ((uint32_t)(j * 64) < nb_ld) L.b[k] = k < nb_ld ? rb[j] : KEY_INF;
+      if ((uint32_t)(j * 64) < na_ld) L.a[k] = ra[j];
+      if ((uint32_t)(j * 64) < nb_ld) L.b[k] = rb[j];
     }
     wave_lds_sync();
-    // every element up to the smaller of the two window maxima is merged now
+    // every element up to the smaller of the two window maxima is merged now:
+    // all of the window that ends lower, and the other one up to that key
     const uint32_t ra_rem = cur.la - ia, rb_rem = cur.lb - ib;
-    const uint32_t lastA = na_ld < ra_rem ? key_of(L.a[na_ld - 1]) : KEY_INF;
-    const uint32_t lastB = nb_ld < rb_rem ? key_of(L.b[nb_ld - 1]) : KEY_INF;
-    const uint32_t bound = lastA < lastB ? lastA : lastB;
-    uint32_t na = 0, nb = 0;
-#pragma unroll
-    for (int j = 0; j < W / 64; ++j) {
-      const uint32_t k = (uint32_t)(j * 64 + lane);
-      if ((uint32_t)(j * 64) < na_ld) na += (uint32_t)__popcll(__ballot(k < na_ld && key_of(ra[j]) <= bound));
-      if ((uint32_t)(j * 64) < nb_ld) nb += (uint32_t)__popcll(__ballot(k < nb_ld && key_of(rb[j]) <= bound));
+    const uint32_t lastA = na_ld < ra_rem ? uni(key_of(L.a[na_ld - 1])) : KEY_INF;
+    const uint32_t lastB = nb_ld < rb_rem ? uni(key_of(L.b[nb_ld - 1])) : KEY_INF;
+    uint32_t na = na_ld, nb = nb_ld;
+    if (lastA < lastB) {
+      if (nb_ld) nb = count_le<W>(L.b, nb_ld, lastA, lane);
+    } else if (lastB < lastA) {
+      if (na_ld) na = count_le<W>(L.a, na_ld, lastB, lane);
     }
     if (lane == 0) {
       L.a[na] = KEY_INF;  // sentinels: the walk never reads past them
@@ -582,7 +609,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
         // batch exhausted: claim the next one (the current item is already in
         // scalars, so bt can be overwritten; this latency is not hidden)
         for (;;) {
-          more = fetch_batch<BAT>(g, lane, phase, bt);
+          more = uni(fetch_batch<BAT>(g, lane, phase, bt));
           if (!more) break;
           int k0 = 0;
           while (k0 < bt.cnt && bcast32(bt.la, k0) + bcast32(bt.lb, k0) == 0) ++k0;
@@ -682,7 +709,8 @@ static int scan_excl(const int64_t* in, int64_t m, int64_t* out, Scratch& scratc
 }
 
 // Kernel variants: LDS window per list x counter array layout x occupancy hint.
-enum Variant { V_W512 = 0, V_W1024 = 1, V_W512_HH = 2, V_W256_HH = 3, V_W512_HH6 = 4, NUM_VARIANTS };
+enum Variant { V_W512 = 0, V_W1024 = 1, V_W512_HH = 2, V_W256_HH = 3, V_W512_HH6 = 4, V_W448_HH7 = 5,
+               V_W384_HH7 = 6, V_W320_HH8 = 7, NUM_VARIANTS };
 
 template <int WAVES, int W, bool HH, int MINW>
 static hipError_t launch_t(const CensusArgs& a, int mode, int groups, hipStream_t s) {
@@ -708,6 +736,9 @@ static hipError_t launch_v(int variant, const CensusArgs& a, int cyc, int groups
     case V_W512_HH: return launch_t<WAVES, 512, true, 1>(a, cyc, groups, s);
     case V_W256_HH: return launch_t<WAVES, 256, true, 1>(a, cyc, groups, s);
     case V_W512_HH6: return launch_t<WAVES, 512, true, 6>(a, cyc, groups, s);
+    case V_W448_HH7: return launch_t<WAVES, 448, true, 7>(a, cyc, groups, s);
+    case V_W384_HH7: return launch_t<WAVES, 384, true, 7>(a, cyc, groups, s);
+    case V_W320_HH8: return launch_t<WAVES, 320, true, 8>(a, cyc, groups, s);
     default: return launch_t<WAVES, 512, false, 1>(a, cyc, groups, s);
   }
 }
@@ -718,6 +749,9 @@ static int occ_v(int variant, int cyc) {
     case V_W512_HH: return occ_t<WAVES, 512, true, 1>(cyc);
     case V_W256_HH: return occ_t<WAVES, 256, true, 1>(cyc);
     case V_W512_HH6: return occ_t<WAVES, 512, true, 6>(cyc);
+    case V_W448_HH7: return occ_t<WAVES, 448, true, 7>(cyc);
+    case V_W384_HH7: return occ_t<WAVES, 384, true, 7>(cyc);
+    case V_W320_HH8: return occ_t<WAVES, 320, true, 8>(cyc);
     default: return occ_t<WAVES, 512, false, 1>(cyc);
   }
 }
