@@ -260,6 +260,9 @@ struct CensusArgs {
 
 constexpr int BATCH = 64;   // work items claimed per queue access
 constexpr int PAD = 1024;   // readable entries past the end of the packed array
+// rounds with at most LOP_S ids in one window and at least LOP_G in the other
+// take the entry-by-entry path (lopsided_round) instead of the merged walk
+constexpr uint32_t LOP_S = 64, LOP_G = 128;
 
 // Per-wavefront LDS: two sorted windows (plus a sentinel slot each) and the
 // class counters, one per (class, lane). HH = true shares each counter between
@@ -505,12 +508,76 @@ __device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, 
   return (pos - start) - steps;
 }
 
+// A round in which one window holds few ids (S, ns of them) and the other many
+// (G, ng): the same classification as the walk, entry by entry instead of in
+// merged order. Each id of S finds its match in G by a branchless lower-bound
+// search and is classified with both flags; every id of G is classified as
+// found in its own list only, in 64-wide chunks, and the match of an S id
+// takes that one-list count back. Counter columns can therefore dip below
+// zero between flushes; flush_wave sums them as signed values. Returns the
+// number of ids found in both lists (per lane).
+template <int W, bool HH>
+__device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
+                                                   uint32_t vq, uint64_t slice, uint32_t col, int lane) {
+  constexpr uint32_t ROW = WaveLds<W, HH>::COLS * 4;  // bytes per class row
+  const bool sA = na <= nb;  // the short window is N(u)'s
+  const uint32_t* S = sA ? L.a : L.b;
+  const uint32_t* G = sA ? L.b : L.a;
+  const uint32_t ns = sA ? na : nb, ng = sA ? nb : na;
+  // class of an id found in G only, by its flag: N(v) only (sA) is counted iff
+  // u < w, N(u) only iff v < w; row table of flag -> class, one byte each
+  const uint32_t thrG = sA ? uq : vq;
+  const uint32_t sel0 = sA ? 2u : 0u;  // flag position in the table index
+  uint32_t rowtbl = 0;
+  for (uint32_t f = 1; f < 4; ++f) rowtbl |= (uint32_t)((slice >> (4u * (f << sel0))) & 15u) << (8u * f);
+  rowtbl = uni(rowtbl);
+  uint32_t* const hcol = L.hist + col;
+  uint32_t inter = 0;
+  for (uint32_t t0 = 0; t0 < ns; t0 += 64) {
+    const uint32_t t = t0 + (uint32_t)lane;
+    const bool act = t < ns;
+    const uint32_t x = S[act ? t : 0];
+    const uint32_t kx = x | 3u;
+    // lower bound of kx in G[0, ng), ng >= 1
+    uint32_t base = 0;
+    for (uint32_t len = ng; len > 1;) {
+      const uint32_t half = len >> 1;
+      base = key_of(G[base + half]) < kx ? base + half : base;
+      len -= half;
+    }
+    const uint32_t r = base + (key_of(G[base]) < kx ? 1u : 0u);
+    const uint32_t gr = G[r];  // G[ng] is the sentinel
+    const bool common = act & (key_of(gr) == kx);
+    const uint32_t fs = x & 3u, fg = common ? gr & 3u : 0u;
+    // canonical selection (Fig. 5 step 2.1.4) for the S id
+    const bool counted = act & (sA | common ? kx > vq : kx > uq);
+    const uint32_t idx = sA ? fs | fg << 2 : fg | fs << 2;
+    const uint32_t cls = counted ? (uint32_t)(slice >> (idx << 2)) & 15u : 0u;
+    atomicAdd(hcol + cls * (ROW / 4), 1u);
+    // the matched G id is counted below as found in G only: take that back
+    const uint32_t gcls = (common & (kx > thrG)) ? (rowtbl >> (8u * fg)) & 15u : 0u;
+    if (common) atomicSub(hcol + gcls * (ROW / 4), 1u);
+    inter += (uint32_t)common;
+  }
+  for (uint32_t j = 0; j * 64 < ng; ++j) {
+    const uint32_t e = j * 64 + (uint32_t)lane;
+    const uint32_t y = G[e];
+    const bool counted = (e < ng) & (y > thrG);
+    const uint32_t sh = counted ? (y & 3u) << 3 : 0u;
+    const uint32_t cls = (rowtbl >> sh) & 15u;
+    atomicAdd(hcol + cls * (ROW / 4), 1u);
+  }
+  return inter;
+}
+
 template <int W, bool HH>
 __device__ void flush_wave(WaveLds<W, HH>& L, int lane, unsigned long long* acc) {
   constexpr int C = WaveLds<W, HH>::COLS;
   wave_lds_sync();
   for (int c = 1; c < 16; ++c) {
-    const uint64_t x = lane < C ? L.hist[c * C + lane] : 0u;
+    // columns are signed: a lopsided round may take a count back from a column
+    // other than the one that received it
+    const uint64_t x = lane < C ? (uint64_t)(int64_t)(int32_t)L.hist[c * C + lane] : 0u;
     const uint64_t sum = wave_sum64(x);
     if (lane == 0 && sum) atomicAdd(&acc[c], (unsigned long long)sum);
   }
@@ -634,7 +701,10 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
       }
       wg = cur.gid;
     }
-    item_inter += merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
+    if (min(na, nb) <= LOP_S && max(na, nb) >= LOP_G)
+      item_inter += lopsided_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
+    else
+      item_inter += merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
     steps += (na + nb) / (HH ? 16 : 32) + 4;
     if (item_done) {
       atomicAdd(&L.hist[(cur.f == 3 ? 2 : 1) * C + col], item_inter);
