@@ -432,16 +432,27 @@ __device__ __forceinline__ void item_of(const Batch& bt, int it, const CensusArg
   x.tid = (int64_t)bcast64((uint64_t)bt.tid, it);
 }
 
-// Issue the global loads of one round's windows into registers (no wait).
+// Buffer resource over n 32-bit words at p: a load past the n-th word returns
+// 0 and does not access memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t words_rsrc(const uint32_t* p, uint32_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(p), (short)0, (int)(n * 4u), 0x00020000);
+}
+
+// Issue the loads of one round's windows into registers (no wait). Every
+// chunk is loaded without a branch; lanes past the window end read 0.
 template <int W>
 __device__ __forceinline__ void load_round(const uint32_t* A, uint32_t na_ld, const uint32_t* B, uint32_t nb_ld,
                                            int lane, uint32_t (&ra)[W / 64], uint32_t (&rb)[W / 64]) {
+  if (na_ld) {
+    const __amdgpu_buffer_rsrc_t r = words_rsrc(A, na_ld);
 #pragma unroll
-  for (int j = 0; j < W / 64; ++j)
-    if ((uint32_t)(j * 64) < na_ld) ra[j] = A[j * 64 + lane];
+    for (int j = 0; j < W / 64; ++j) ra[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (j * 64 + lane) * 4, 0, 0);
+  }
+  if (nb_ld) {
+    const __amdgpu_buffer_rsrc_t r = words_rsrc(B, nb_ld);
 #pragma unroll
-  for (int j = 0; j < W / 64; ++j)
-    if ((uint32_t)(j * 64) < nb_ld) rb[j] = B[j * 64 + lane];
+    for (int j = 0; j < W / 64; ++j) rb[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (j * 64 + lane) * 4, 0, 0);
+  }
 }
 
 // Number of entries of the sorted window x[0, n) with key <= bound, 0 < n <= W:
@@ -519,53 +530,64 @@ __device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, 
 template <int W, bool HH>
 __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
                                                    uint32_t vq, uint64_t slice, uint32_t col, int lane) {
-  constexpr uint32_t ROW = WaveLds<W, HH>::COLS * 4;  // bytes per class row
+  constexpr uint32_t C = WaveLds<W, HH>::COLS;
   const bool sA = na <= nb;  // the short window is N(u)'s
   const uint32_t* S = sA ? L.a : L.b;
   const uint32_t* G = sA ? L.b : L.a;
   const uint32_t ns = sA ? na : nb, ng = sA ? nb : na;
-  // class of an id found in G only, by its flag: N(v) only (sA) is counted iff
-  // u < w, N(u) only iff v < w; row table of flag -> class, one byte each
+  // class of an id found in G only, by its flag f: N(v) only (sA) is counted
+  // iff u < w, N(u) only iff v < w. Nibble f of rowtbl holds that class
+  // (nibble 0: not counted), and the four nibbles are repeated at bit 16 so
+  // that a bit-field extract at offset (y << 2) mod 32 finds them whatever the
+  // lowest id bit of y.
   const uint32_t thrG = sA ? uq : vq;
-  const uint32_t sel0 = sA ? 2u : 0u;  // flag position in the table index
+  const uint32_t sel0 = sA ? 2u : 0u;  // position of the flag in the table index
   uint32_t rowtbl = 0;
-  for (uint32_t f = 1; f < 4; ++f) rowtbl |= (uint32_t)((slice >> (4u * (f << sel0))) & 15u) << (8u * f);
-  rowtbl = uni(rowtbl);
+  for (uint32_t f = 1; f < 4; ++f) rowtbl |= (uint32_t)((slice >> (4u * (f << sel0))) & 15u) << (4u * f);
+  rowtbl = uni(rowtbl | rowtbl << 16);
   uint32_t* const hcol = L.hist + col;
+  const char* const Gb = (const char*)G;
   uint32_t inter = 0;
   for (uint32_t t0 = 0; t0 < ns; t0 += 64) {
     const uint32_t t = t0 + (uint32_t)lane;
     const bool act = t < ns;
     const uint32_t x = S[act ? t : 0];
-    const uint32_t kx = x | 3u;
-    // lower bound of kx in G[0, ng), ng >= 1
+    const uint32_t kx = x | 3u, x0 = x & ~3u;
+    // lower bound of x's id in G[0, ng), ng >= 1: a packed word is below x0
+    // iff its id is below x's; the base is kept in bytes
     uint32_t base = 0;
     for (uint32_t len = ng; len > 1;) {
       const uint32_t half = len >> 1;
-      base = key_of(G[base + half]) < kx ? base + half : base;
+      const uint32_t probe = base + half * 4u;
+      base = *(const uint32_t*)(Gb + probe) < x0 ? probe : base;
       len -= half;
     }
-    const uint32_t r = base + (key_of(G[base]) < kx ? 1u : 0u);
-    const uint32_t gr = G[r];  // G[ng] is the sentinel
+    const uint32_t gb = *(const uint32_t*)(Gb + base);
+    const uint32_t gr = gb < x0 ? *(const uint32_t*)(Gb + base + 4u) : gb;  // G[ng] is the sentinel
     const bool common = act & (key_of(gr) == kx);
     const uint32_t fs = x & 3u, fg = common ? gr & 3u : 0u;
     // canonical selection (Fig. 5 step 2.1.4) for the S id
     const bool counted = act & (sA | common ? kx > vq : kx > uq);
     const uint32_t idx = sA ? fs | fg << 2 : fg | fs << 2;
     const uint32_t cls = counted ? (uint32_t)(slice >> (idx << 2)) & 15u : 0u;
-    atomicAdd(hcol + cls * (ROW / 4), 1u);
+    atomicAdd(hcol + cls * C, 1u);
     // the matched G id is counted below as found in G only: take that back
-    const uint32_t gcls = (common & (kx > thrG)) ? (rowtbl >> (8u * fg)) & 15u : 0u;
-    if (common) atomicSub(hcol + gcls * (ROW / 4), 1u);
+    const uint32_t gcls = (common & (kx > thrG)) ? (rowtbl >> (4u * fg)) & 15u : 0u;
+    if (common) atomicSub(hcol + gcls * C, 1u);
     inter += (uint32_t)common;
   }
-  for (uint32_t j = 0; j * 64 < ng; ++j) {
-    const uint32_t e = j * 64 + (uint32_t)lane;
+  // ids of G, classified as found in G only, 64 per step
+  const uint32_t nfull = ng & ~63u;
+  uint32_t e = (uint32_t)lane;
+  for (; e < nfull; e += 64) {
     const uint32_t y = G[e];
-    const bool counted = (e < ng) & (y > thrG);
-    const uint32_t sh = counted ? (y & 3u) << 3 : 0u;
-    const uint32_t cls = (rowtbl >> sh) & 15u;
-    atomicAdd(hcol + cls * (ROW / 4), 1u);
+    const uint32_t off = y > thrG ? y << 2 : 0u;
+    atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
+  }
+  if (nfull < ng) {
+    const uint32_t y = G[e];
+    const uint32_t off = (e < ng) & (y > thrG) ? y << 2 : 0u;
+    atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
   }
   return inter;
 }
@@ -635,13 +657,13 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   uint32_t na_ld = 0, nb_ld = 0;
 
   for (;;) {
-    // ---- stage the loaded round in LDS (register slots past the window hold
-    // stale values; the walk stops at the sentinels and never reads them)
+    // ---- stage the loaded round in LDS (slots past the window get zeros or
+    // stale values; every reader stops at the window end or its sentinel)
 #pragma unroll
     for (int j = 0; j < W / 64; ++j) {
       const uint32_t k = (uint32_t)(j * 64 + lane);
-      if ((uint32_t)(j * 64) < na_ld) L.a[k] = ra[j];
-      if ((uint32_t)(j * 64) < nb_ld) L.b[k] = rb[j];
+      L.a[k] = ra[j];
+      L.b[k] = rb[j];
     }
     wave_lds_sync();
     // every element up to the smaller of the two window maxima is merged now:
