@@ -554,13 +554,24 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
     const uint32_t x = S[act ? t : 0];
     const uint32_t kx = x | 3u, x0 = x & ~3u;
     // lower bound of x's id in G[0, ng), ng >= 1: a packed word is below x0
-    // iff its id is below x's; the base is kept in bytes
+    // iff its id is below x's; the base is kept in bytes. A full window (the
+    // usual case) takes a fixed, unrolled sequence of halvings.
     uint32_t base = 0;
-    for (uint32_t len = ng; len > 1;) {
-      const uint32_t half = len >> 1;
-      const uint32_t probe = base + half * 4u;
-      base = *(const uint32_t*)(Gb + probe) < x0 ? probe : base;
-      len -= half;
+    if (ng == (uint32_t)W) {
+#pragma unroll
+      for (uint32_t len = W; len > 1;) {
+        const uint32_t half = len >> 1;
+        const uint32_t probe = base + half * 4u;
+        base = *(const uint32_t*)(Gb + probe) < x0 ? probe : base;
+        len -= half;
+      }
+    } else {
+      for (uint32_t len = ng; len > 1;) {
+        const uint32_t half = len >> 1;
+        const uint32_t probe = base + half * 4u;
+        base = *(const uint32_t*)(Gb + probe) < x0 ? probe : base;
+        len -= half;
+      }
     }
     const uint32_t gb = *(const uint32_t*)(Gb + base);
     const uint32_t gr = gb < x0 ? *(const uint32_t*)(Gb + base + 4u) : gb;  // G[ng] is the sentinel
@@ -579,6 +590,15 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
   // ids of G, classified as found in G only, 64 per step
   const uint32_t nfull = ng & ~63u;
   uint32_t e = (uint32_t)lane;
+  if (nfull == (uint32_t)W) {
+#pragma unroll
+    for (int j = 0; j < W / 64; ++j) {
+      const uint32_t y = G[j * 64 + lane];
+      const uint32_t off = y > thrG ? y << 2 : 0u;
+      atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
+    }
+    return inter;
+  }
   for (; e < nfull; e += 64) {
     const uint32_t y = G[e];
     const uint32_t off = y > thrG ? y << 2 : 0u;
