@@ -85,6 +85,43 @@ def test_hub_heavy_star_and_clique(torch_cuda):
         assert gpu_census(g, hub_threshold=thr, chunk=ch)[0] == want
 
 
+def _round_paths_graph():
+    """Hubs at both ends of the id range and in the middle, two of them with
+    largely shared neighbourhoods, over a sparse random background: the census
+    then has lopsided rounds with the short window on either side, full and
+    partial long windows, and balanced rounds with many common ids."""
+    rng = np.random.default_rng(21)
+    n = 6000
+    arcs = set()
+    def add(a, b):
+        if a != b:
+            arcs.add((int(a), int(b)))
+    for hub, size in ((0, 3100), (n - 1, 2600), (3000, 1500), (3001, 1400)):
+        for w in rng.choice(n, size=size, replace=False):
+            if rng.random() < 0.5:
+                add(hub, w)
+            else:
+                add(w, hub)
+            if rng.random() < 0.15:
+                add(w, hub) if (hub, w) in arcs else add(hub, w)
+    for _ in range(12000):
+        a, b = rng.integers(0, n, size=2)
+        add(a, b)
+    s = np.array([a for a, _ in arcs], np.int32)
+    d = np.array([b for _, b in arcs], np.int32)
+    return graphs.build_csr(n, s, d)
+
+
+def test_round_paths_all_variants(torch_cuda):
+    g = _round_paths_graph()
+    want = oracle.census(g)
+    for variant in range(1, 9):
+        for thr, ch in ((-1, 0), (700, 256)):
+            got, st, tm = gpu_census(g, kernel_variant=variant, hub_threshold=thr, chunk=ch)
+            assert got == want, (variant, thr)
+            assert st == 0
+
+
 def test_deterministic_repeats(torch_cuda):
     g = graphs.rmat(14, 8, seed=2, recip_p=0.1)
     want = oracle.census_mt(g)
