@@ -240,8 +240,9 @@ struct CensusArgs {
   int64_t n;
   const int64_t* off;
   const uint32_t* packed;
-  const uint64_t* tasks;
-  const int64_t* order;  // optional permutation of task indices (schedules)
+  const uint64_t* tasks;   // the task queue (CSR order, or a schedule's order)
+  const uint64_t* htasks;  // tasks in CSR order, indexed by the hub list
+  const int64_t* order;    // optional: queue position -> CSR task index
   int64_t ntasks;
   const uint64_t* hub_task;
   const int64_t* hub_pre;  // [nhub+1] exclusive prefix of chunk counts
@@ -350,7 +351,7 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
         }
         const int64_t c = item - g.hub_pre[lo];
         bt.tid = (int64_t)g.hub_task[lo];
-        const uint64_t tk = g.tasks[bt.tid] & ~HUB_BIT;
+        const uint64_t tk = g.htasks[bt.tid] & ~HUB_BIT;
         const uint32_t u = (uint32_t)(tk >> 32);
         const int64_t au = g.off[u];
         const uint32_t dla = (uint32_t)(g.off[u + 1] - au);
@@ -1001,11 +1002,16 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
       }
     }
   }
+  // A schedule reorders the task words themselves, so that the queue is read
+  // sequentially; with per-task cycle recording it is an index permutation
+  // instead, which keeps the cycles in CSR task order.
   int64_t* order = nullptr;
+  uint64_t* perm = nullptr;
   if (ntasks > 0 && o.schedule != TRIAD_SCHED_PLAIN) {
-    ALLOC(order, ntasks);
+    if (o.task_cycles) ALLOC(order, ntasks);
+    else ALLOC(perm, ntasks);
     const int mode = (o.schedule == TRIAD_SCHED_LEARNED && o.model) ? 2 : 1;
-    if (int st = build_order(mode, o.model, n, off, packed, tasks, ntasks, order, scratch, s)) return st;
+    if (int st = build_order(mode, o.model, n, off, packed, tasks, ntasks, order, perm, scratch, s)) return st;
   }
   ev.rec(2, s);
   int groups = 0;
@@ -1014,7 +1020,8 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.n = n;
     a.off = off;
     a.packed = packed;
-    a.tasks = tasks;
+    a.tasks = perm ? perm : tasks;
+    a.htasks = tasks;
     a.order = order;
     a.ntasks = ntasks;
     a.hub_task = hub_task;
@@ -1208,6 +1215,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   a.off = off;
   a.packed = packed;
   a.tasks = tasks;
+  a.htasks = tasks;
   a.order = nullptr;
   a.ntasks = ntasks;
   a.hub_task = nullptr;

@@ -226,19 +226,37 @@ __global__ void k_zero_f32(float* p, int64_t m) {
 
 // ---------------------------------------------------------------- schedule
 
-// Cost bin of every non-split task: 4 bins per octave of the cost
-// (mode 1: d(u)+d(v); mode 2: the model's predicted cycles, whose log2 it
-// outputs). Split tasks get bin 0 (they are skipped by the census queue).
-// The weights are read from global memory at wave-uniform addresses, so they
-// arrive through the scalar cache and each multiply-add takes one VALU op.
-__global__ void __launch_bounds__(256) k_task_bins(int mode, const float* __restrict__ gw, const int64_t* __restrict__ off,
-                            const uint32_t* __restrict__ packed, const uint64_t* __restrict__ tasks, int64_t ntasks,
-                            uint8_t* __restrict__ bin, unsigned long long* __restrict__ counts) {
-  __shared__ unsigned int cnt[SCHED_BINS];
-  for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) cnt[b] = 0;
+// Tasks are binned by cost, one bin per octave (mode 1: d(u)+d(v); mode 2: the
+// model's predicted cycles, whose log2 it outputs), and laid out costliest bin
+// first. The layout is a stable counting sort: within a bin the tasks keep
+// their CSR order, so the tasks of one vertex u stay together and its list
+// N(u) keeps being reused from L2 by neighbouring queue positions. Work is cut
+// into chunks of SCHED_CHUNK tasks, one wavefront each.
+constexpr int64_t SCHED_CHUNK = 8192;
+// Bins per octave of the cost. Finer bins order the long tasks more exactly but
+// scatter the tasks of one vertex u (whose costs differ by d(v)) over more of
+// the queue, and N(u) is then fetched from HBM more often.
+constexpr float SCHED_BPO = 1.0f;
+// The learned schedule evaluates the network only for tasks of at least this
+// many merge entries (about one LDS round); shorter ones take the lowest bin,
+// i.e. they run last, in CSR order.
+constexpr uint32_t SCHED_MLP_MIN = 512;
+
+// Cost bin of every task (split tasks: bin 0, the census queue skips them) and
+// each chunk's count per bin, bin-major: cnt[b * nchunks + c]. The weights are
+// read at wave-uniform addresses, so they arrive through the scalar cache and
+// each multiply-add takes one VALU op.
+__global__ void __launch_bounds__(64) k_task_bins(int mode, const float* __restrict__ gw, const int64_t* __restrict__ off,
+                                                  const uint32_t* __restrict__ packed, const uint64_t* __restrict__ tasks,
+                                                  int64_t ntasks, int64_t nchunks, uint8_t* __restrict__ bin,
+                                                  unsigned int* __restrict__ cnt) {
+  __shared__ unsigned int h[SCHED_BINS];
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  for (int b = lane; b < SCHED_BINS; b += 64) h[b] = 0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntasks; t += stride) {
+  const int64_t t0 = c * SCHED_CHUNK, t1 = min(t0 + SCHED_CHUNK, ntasks);
+  for (int64_t t = t0 + lane; t < t1; t += 64) {
     const uint64_t tk = tasks[t];
     int b = 0;
     if (!(tk & HUB_BIT)) {
@@ -247,59 +265,96 @@ __global__ void __launch_bounds__(256) k_task_bins(int mode, const float* __rest
       const uint32_t du = (uint32_t)(off[u + 1] - au);
       const uint32_t v = packed[au + k] >> 2;
       const uint32_t dv = (uint32_t)(off[v + 1] - off[v]);
-      float c;
-      if (mode == 2) {
+      if (mode != 2) {
+        b = (int)floorf(log2f((float)du + (float)dv) * SCHED_BPO);
+      } else if (du + dv >= SCHED_MLP_MIN) {
         float x[NI];
         task_features(du, dv, du - k - 1, x);
-        c = mlp_forward(gw, x);
-      } else {
-        c = log2f((float)du + (float)dv);
+        b = (int)floorf(mlp_forward(gw, x) * SCHED_BPO);
       }
-      b = (int)floorf(c * 4.0f);
       b = b < 0 ? 0 : (b >= SCHED_BINS ? SCHED_BINS - 1 : b);
     }
     bin[t] = (uint8_t)b;
-    atomicAdd(&cnt[b], 1u);
+    atomicAdd(&h[b], 1u);
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x)
-    if (cnt[b]) atomicAdd(&counts[b], (unsigned long long)cnt[b]);
+  for (int b = lane; b < SCHED_BINS; b += 64) cnt[(int64_t)b * nchunks + c] = h[b];
 }
 
-// Bin starts for descending bin order (costliest first).
-__global__ void k_bin_starts(unsigned long long* counts) {
+// Per bin (one block each): exclusive prefix of the chunk counts, in place as
+// 64-bit offsets within the bin, and the bin's total.
+__global__ void __launch_bounds__(256) k_bin_scan(const unsigned int* __restrict__ cnt, int64_t nchunks,
+                                                  unsigned long long* __restrict__ pre, unsigned long long* __restrict__ total) {
+  __shared__ unsigned long long part[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int64_t per = (nchunks + 255) / 256, lo = min((int64_t)t * per, nchunks), hi = min(lo + per, nchunks);
+  const unsigned int* row = cnt + (int64_t)b * nchunks;
+  unsigned long long sum = 0;
+  for (int64_t c = lo; c < hi; ++c) sum += row[c];
+  part[t] = sum;
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long run = 0;
+    for (int i = 0; i < 256; ++i) {
+      const unsigned long long x = part[i];
+      part[i] = run;
+      run += x;
+    }
+    total[b] = run;
+  }
+  __syncthreads();
+  unsigned long long run = part[t];
+  unsigned long long* out = pre + (int64_t)b * nchunks;
+  for (int64_t c = lo; c < hi; ++c) {
+    out[c] = run;
+    run += row[c];
+  }
+}
+
+// Start of each bin in the costliest-first layout.
+__global__ void k_bin_starts(unsigned long long* total) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   unsigned long long run = 0;
   for (int b = SCHED_BINS - 1; b >= 0; --b) {
-    const unsigned long long c = counts[b];
-    counts[b] = run;
+    const unsigned long long c = total[b];
+    total[b] = run;
     run += c;
   }
 }
 
-// Scatter task ids into their bins: one global reservation per (block, bin),
-// then block-local slots.
-__global__ void k_bin_scatter(const uint8_t* __restrict__ bin, int64_t ntasks, unsigned long long* __restrict__ cursor,
-                              int64_t* __restrict__ order) {
-  __shared__ unsigned int cnt[SCHED_BINS];
-  __shared__ unsigned long long base[SCHED_BINS];
-  const int64_t per_block = (int64_t)blockDim.x * 16;
-  for (int64_t t0 = (int64_t)blockIdx.x * per_block; t0 < ntasks; t0 += (int64_t)gridDim.x * per_block) {
-    for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) cnt[b] = 0;
-    __syncthreads();
-    const int64_t t1 = min(t0 + per_block, ntasks);
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) atomicAdd(&cnt[bin[t]], 1u);
-    __syncthreads();
-    for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) {
-      base[b] = cnt[b] ? atomicAdd(&cursor[b], (unsigned long long)cnt[b]) : 0ull;
-      cnt[b] = 0;
+// Stable scatter, one wavefront per chunk, 64 tasks per step: lanes holding
+// the same bin are ranked by lane order (their bin equality mask is built
+// from one ballot per bin bit), after the chunk's earlier tasks of that bin.
+// Writes either the task words themselves in schedule order (perm) or their
+// CSR indices (order).
+__global__ void __launch_bounds__(64) k_bin_scatter(const uint8_t* __restrict__ bin, const uint64_t* __restrict__ tasks,
+                                                    int64_t ntasks, int64_t nchunks, const unsigned long long* __restrict__ pre,
+                                                    const unsigned long long* __restrict__ start, int64_t* __restrict__ order,
+                                                    uint64_t* __restrict__ perm) {
+  __shared__ unsigned long long next[SCHED_BINS];
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  for (int b = lane; b < SCHED_BINS; b += 64) next[b] = start[b] + pre[(int64_t)b * nchunks + c];
+  __syncthreads();
+  const int64_t t0 = c * SCHED_CHUNK, t1 = min(t0 + SCHED_CHUNK, ntasks);
+  const uint64_t below = (1ull << lane) - 1;
+  for (int64_t s0 = t0; s0 < t1; s0 += 64) {
+    const int64_t t = s0 + lane;
+    const bool act = t < t1;
+    const uint32_t b = act ? bin[t] : (uint32_t)SCHED_BINS;  // no bin matches an idle lane
+    uint64_t eq = ~0ull;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t m = __ballot((b >> k) & 1u);
+      eq &= ((b >> k) & 1u) ? m : ~m;
+    }
+    if (act) {
+      const unsigned long long pos = next[b] + (unsigned long long)__popcll(eq & below);
+      if (perm) perm[pos] = tasks[t];
+      else order[pos] = t;
     }
     __syncthreads();
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-      const int b = bin[t];
-      const unsigned int r = atomicAdd(&cnt[b], 1u);
-      order[base[b] + r] = t;
-    }
+    if (act && (eq >> lane) == 1ull) next[b] += (unsigned long long)__popcll(eq);  // last lane of its group
     __syncthreads();
   }
 }
@@ -312,18 +367,24 @@ static int grid_of(int64_t work, int threads, int cap) {
 }
 
 int build_order(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* packed,
-                const uint64_t* tasks, int64_t ntasks, int64_t* order, Scratch& scratch, hipStream_t s) {
+                const uint64_t* tasks, int64_t ntasks, int64_t* order, uint64_t* perm, Scratch& scratch, hipStream_t s) {
   (void)n;
   if (ntasks <= 0) return TRIAD_OK;
+  const int64_t nchunks = (ntasks + SCHED_CHUNK - 1) / SCHED_CHUNK;
   uint8_t* bin = nullptr;
-  unsigned long long* counts = nullptr;
+  unsigned int* cnt = nullptr;
+  unsigned long long* pre = nullptr;
+  unsigned long long* start = nullptr;
   ALLOC(bin, ntasks);
-  ALLOC(counts, SCHED_BINS);
-  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, (float*)counts, (int64_t)(2 * SCHED_BINS));
-  hipLaunchKernelGGL(k_task_bins, dim3(grid_of(ntasks, 256, 16384)), dim3(256), 0, s, mode, model, off, packed, tasks,
-                     ntasks, bin, counts);
-  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, s, counts);
-  hipLaunchKernelGGL(k_bin_scatter, dim3(grid_of(ntasks, 256 * 16, 8192)), dim3(256), 0, s, bin, ntasks, counts, order);
+  ALLOC(cnt, nchunks * SCHED_BINS);
+  ALLOC(pre, nchunks * SCHED_BINS);
+  ALLOC(start, SCHED_BINS);
+  hipLaunchKernelGGL(k_task_bins, dim3((unsigned)nchunks), dim3(64), 0, s, mode, model, off, packed, tasks, ntasks, nchunks,
+                     bin, cnt);
+  hipLaunchKernelGGL(k_bin_scan, dim3(SCHED_BINS), dim3(256), 0, s, cnt, nchunks, pre, start);
+  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, s, start);
+  hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)nchunks), dim3(64), 0, s, bin, tasks, ntasks, nchunks, pre, start, order,
+                     perm);
   HIPCHK(hipGetLastError());
   return TRIAD_OK;
 }

@@ -86,11 +86,13 @@ struct Scratch {
 // bit 63 marks a task that is split into chunks (merged from the hub list).
 constexpr uint64_t HUB_BIT = 1ull << 63;
 
-// Schedule: a permutation `order` of the task indices, longest-first by a cost
-// key binned into SCHED_BINS bins (counting sort). mode 1 = d(u)+d(v),
-// mode 2 = the learned model's predicted log2 cycles (model = device weights).
+// Schedule: the tasks longest-first by a cost key binned into SCHED_BINS bins
+// (stable counting sort: CSR order within a bin). mode 1 = d(u)+d(v), mode 2 =
+// the learned model's predicted log2 cycles (model = device weights).
 constexpr int SCHED_BINS = 128;
+// Exactly one of order (CSR task indices) and perm (the task words) is written,
+// in schedule order.
 int build_order(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* packed,
-                const uint64_t* tasks, int64_t ntasks, int64_t* order, Scratch& scratch, hipStream_t s);
+                const uint64_t* tasks, int64_t ntasks, int64_t* order, uint64_t* perm, Scratch& scratch, hipStream_t s);
 
 }  // namespace triad
