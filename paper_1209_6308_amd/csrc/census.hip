@@ -889,7 +889,17 @@ static int census_groups(int waves, int variant, int cyc, int requested) {
 static int default_variant() {
   const char* e = getenv("TRIAD_VARIANT");
   if (e && *e >= '0' && *e < '0' + NUM_VARIANTS) return *e - '0';
-  return V_W512_HH6;
+  return V_W448_HH7;
+}
+
+// The kernel variant of a call and its wavefronts per workgroup: 448-entry
+// windows at 7 wavefronts per SIMD run best with two wavefronts per workgroup.
+static int pick_variant(const triad_opts& o) {
+  return o.kernel_variant > 0 && o.kernel_variant <= NUM_VARIANTS ? o.kernel_variant - 1 : default_variant();
+}
+static int pick_waves(const triad_opts& o, int variant) {
+  if (o.waves_per_group) return o.waves_per_group;
+  return variant == V_W448_HH7 ? 2 : 1;
 }
 
 struct Events {
@@ -926,7 +936,8 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   if (!off || !d_out || (nnz > 0 && (!nbr || !flg))) return fail(TRIAD_EINVAL, "NULL pointer argument");
   if (o.validate < 0 || o.validate > 1) return fail(TRIAD_EINVAL, "validate must be 0 or 1");
   if (o.schedule < 0 || o.schedule > 2) return fail(TRIAD_EINVAL, "unknown schedule");
-  int waves = o.waves_per_group ? o.waves_per_group : 1;
+  const int variant = pick_variant(o);
+  const int waves = pick_waves(o, variant);
   if (waves != 1 && waves != 2 && waves != 4) return fail(TRIAD_EINVAL, "waves_per_group must be 1, 2 or 4");
   const int64_t chunk = o.chunk > 0 ? o.chunk : 32768;
   const int64_t hub_thr = o.hub_threshold == 0 ? 65536 : o.hub_threshold;
@@ -1034,7 +1045,6 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.wave_span = o.wave_span;
     a.err = err;
     a.cls = class_slices();
-    const int variant = o.kernel_variant > 0 && o.kernel_variant <= NUM_VARIANTS ? o.kernel_variant - 1 : default_variant();
     groups = census_groups(waves, variant, a.cycles != nullptr ? 1 : 0, o.grid_groups);
     HIPCHK(launch_census(waves, variant, a, groups, s));
     HIPCHK(hipGetLastError());
@@ -1187,9 +1197,9 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   if (G < 1 || nv < 0 || nv >= ((int64_t)1 << 30) || nnz < 0 || nnz >= ((int64_t)1 << 40))
     return fail(TRIAD_EINVAL, "bad batch sizes");
   if (!vbase || !off || !d_out || (nnz > 0 && (!nbr || !flg)) || !out_plan) return fail(TRIAD_EINVAL, "NULL pointer");
-  int waves = o.waves_per_group ? o.waves_per_group : 1;
+  const int variant = pick_variant(o);
+  const int waves = pick_waves(o, variant);
   if (waves != 1 && waves != 2 && waves != 4) return fail(TRIAD_EINVAL, "waves_per_group must be 1, 2 or 4");
-  const int variant = o.kernel_variant > 0 && o.kernel_variant <= NUM_VARIANTS ? o.kernel_variant - 1 : default_variant();
   DeviceInfo di;
   if (int st = device_info(&di)) return st;
   triad_batch_plan* p = new triad_batch_plan;
@@ -1415,10 +1425,10 @@ int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t* d_vb
   HIPCHK(hipEventCreate(&e1));
   float best_ms = 1e30f;
   triad_opts bo{};
-  const int variants[3] = {V_W512_HH6 + 1, V_W512 + 1, V_W512_HH + 1};
+  const int variants[4] = {V_W448_HH7 + 1, V_W512_HH6 + 1, V_W512 + 1, V_W512_HH + 1};
   const int wavess[2] = {1, 2};
   int status = TRIAD_OK;
-  for (int vi = 0; vi < 3 && status == TRIAD_OK; ++vi)
+  for (int vi = 0; vi < 4 && status == TRIAD_OK; ++vi)
     for (int wi = 0; wi < 2 && status == TRIAD_OK; ++wi)
       for (int gm = 1; gm <= 2; ++gm) {
         triad_opts o{};
