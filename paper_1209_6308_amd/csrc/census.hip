@@ -9,8 +9,9 @@
 //               Sec. 6 / Fig. 7, built once on the device)
 //   scan        exclusive prefix of tasks(u): the collapsed (u,v) task space
 //               of Fig. 5 steps 2 and 2.1
-//   k_emit      task list in CSR order; tasks whose merge length d(u)+d(v)
-//               exceeds the hub threshold go to the hub list instead
+//   k_emit_*    task list in CSR order (short rows one lane each, long rows one
+//               wavefront each); tasks whose merge length d(u)+d(v) exceeds
+//               the hub threshold go to the hub list instead
 //   k_census    persistent wavefronts: hub chunks first, then tasks; each
 //               item merges a range of N(u) with a range of N(v)
 //   k_finalize  003 = C(n,3) - sum of the rest, in two 64-bit words
@@ -198,40 +199,119 @@ __global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t m, const in
 }
 
 // --------------------------------------------------------------- task list
-// One wavefront per row: tasks of row u are its entries above u, written in
-// CSR order as (u << 32 | local index). Tasks longer than the hub threshold
-// are flagged and appended to the hub list with their chunk counts.
-__global__ void k_emit(int64_t n, const int64_t* __restrict__ off, const uint32_t* __restrict__ packed,
-                       const uint32_t* __restrict__ ustart, const int64_t* __restrict__ tpre,
-                       uint64_t* __restrict__ tasks, int64_t hub_threshold, int64_t chunk,
-                       uint64_t* __restrict__ hub_task, int64_t* __restrict__ hub_nch,
-                       unsigned long long* __restrict__ hub_count, const uint32_t* __restrict__ err) {
-  if (*err) return;
+
+// Task list in CSR order (and the hub list): the tasks of row u are its
+// entries above u, written as (u << 32 | local index); tasks longer than the
+// hub threshold are flagged and appended to the hub list with their chunk
+// counts. Rows with at most EMIT_SHORT
+// tasks are emitted by one lane each (k_emit_short, which lists the longer
+// rows); each longer row by a whole wavefront (k_emit_long). Hub tasks are
+// appended with one atomic per wavefront step.
+constexpr int64_t EMIT_SHORT = 32;
+
+struct EmitArgs {
+  int64_t n;
+  const int64_t* off;
+  const uint32_t* packed;
+  const uint32_t* ustart;
+  const int64_t* tpre;
+  uint64_t* tasks;
+  int64_t hub_threshold;  // < 0: no hub list
+  int64_t chunk;
+  uint64_t* hub_task;
+  int64_t* hub_nch;
+  unsigned long long* hub_count;
+  uint32_t* long_rows;
+  unsigned long long* long_count;
+  const uint32_t* err;
+};
+
+// Reserves popcount(mask) slots of a global list for the lanes in mask; every
+// lane gets the first slot (wave-uniform) and adds its rank among them.
+__device__ __forceinline__ uint64_t wave_reserve(unsigned long long* ctr, uint64_t mask, int lane) {
+  uint64_t base = 0;
+  if (lane == 0) base = atomicAdd(ctr, (unsigned long long)__popcll(mask));
+  return bcast64(base, 0);
+}
+
+// One task per active lane: row u (entries from b, degree du), k = index of v
+// in the row, t = task index. All lanes of the wavefront call it together.
+__device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int lane, int64_t u, int64_t b, int64_t du,
+                                          uint32_t k, int64_t t) {
+  uint64_t tk = ((uint64_t)u << 32) | k;
+  if (e.hub_threshold >= 0) {
+    bool hub = false;
+    int64_t L = 0;
+    if (act) {
+      const uint32_t v = e.packed[b + k] >> 2;
+      L = du + (e.off[v + 1] - e.off[v]);
+      hub = L > e.hub_threshold;
+    }
+    const uint64_t hm = __ballot(hub);
+    if (hm) {
+      const uint64_t base = wave_reserve(e.hub_count, hm, lane);
+      if (hub) {
+        const uint64_t slot = base + (uint64_t)__popcll(hm & ((1ull << lane) - 1));
+        e.hub_task[slot] = (uint64_t)t;
+        e.hub_nch[slot] = (L + e.chunk - 1) / e.chunk;
+        tk |= HUB_BIT;
+      }
+    }
+  }
+  if (act) e.tasks[t] = tk;
+}
+
+__global__ void k_emit_short(EmitArgs e) {
+  if (*e.err) return;
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t u = wave; u < n; u += nwave) {
-    const int64_t b = off[u];
-    const int64_t du = off[u + 1] - b;
-    const uint32_t s = ustart[u];
-    const int64_t t0 = tpre[u];
+  for (int64_t ub = wave * 64; ub < e.n; ub += nwave * 64) {
+    const int64_t u = ub + lane;
+    int64_t b = 0, du = 0, t0 = 0, cnt = 0;
+    uint32_t s = 0;
+    if (u < e.n) {
+      b = e.off[u];
+      du = e.off[u + 1] - b;
+      s = e.ustart[u];
+      t0 = e.tpre[u];
+      cnt = du - s;
+    }
+    const bool lng = cnt > EMIT_SHORT;
+    const uint64_t lm = __ballot(lng);
+    if (lm) {
+      const uint64_t base = wave_reserve(e.long_count, lm, lane);
+      if (lng) e.long_rows[base + (uint64_t)__popcll(lm & ((1ull << lane) - 1))] = (uint32_t)u;
+    }
+    const int64_t mine = lng ? 0 : cnt;
+    for (int64_t j = 0; __ballot(j < mine) != 0; ++j)
+      emit_task(e, j < mine, lane, u, b, du, s + (uint32_t)j, t0 + j);
+  }
+}
+
+__global__ void k_emit_long(EmitArgs e) {
+  if (*e.err) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t nl = (int64_t)*e.long_count;
+  for (int64_t r = wave; r < nl; r += nwave) {
+    const int64_t u = e.long_rows[r];
+    const int64_t b = e.off[u], du = e.off[u + 1] - b, t0 = e.tpre[u];
+    const uint32_t s = e.ustart[u];
     const int64_t cnt = du - s;
-    for (int64_t i = lane; i < cnt; i += 64) {
-      uint32_t k = s + (uint32_t)i;
-      uint64_t tk = ((uint64_t)u << 32) | k;
-      if (hub_threshold >= 0) {
-        uint32_t v = packed[b + k] >> 2;
-        int64_t L = du + (off[v + 1] - off[v]);
-        if (L > hub_threshold) {
-          unsigned long long h = atomicAdd(hub_count, 1ull);
-          hub_task[h] = (uint64_t)(t0 + i);
-          hub_nch[h] = (L + chunk - 1) / chunk;
-          tk |= HUB_BIT;
-        }
-      }
-      tasks[t0 + i] = tk;
+    for (int64_t i0 = 0; i0 < cnt; i0 += 64) {
+      const int64_t i = i0 + lane;
+      emit_task(e, i < cnt, lane, u, b, du, s + (uint32_t)i, t0 + i);
     }
   }
+}
+
+static void launch_emit(const EmitArgs& e, hipStream_t s) {
+  const int64_t waves_short = (e.n + 63) / 64;
+  const int blocks_short = (int)std::max<int64_t>(1, std::min<int64_t>((waves_short + 3) / 4, 65536));
+  k_emit_short<<<blocks_short, 256, 0, s>>>(e);
+  k_emit_long<<<16384, 256, 0, s>>>(e);
 }
 
 // ------------------------------------------------------------ the census
@@ -951,9 +1031,9 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   uint32_t* err = nullptr;
   unsigned long long* acc = nullptr;  // [16] census accumulators + [2] queue counters + [1] hub count
   ALLOC(err, 1);
-  ALLOC(acc, 19);
+  ALLOC(acc, 20);  // 16 classes, 2 queue counters, hub tasks, long rows
   k_fill_u32<<<1, 64, 0, s>>>(err, 1, 0);
-  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)acc, 19, 0);
+  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)acc, 20, 0);
   uint64_t clo, chi;
   choose3(n, &clo, &chi);
   ev.rec(0, s);
@@ -1000,8 +1080,11 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     ALLOC(hub_task, hub_cap);
     ALLOC(hub_nch, hub_cap);
     ALLOC(hub_pre, hub_cap + 1);
-    k_emit<<<grid_for(n * 64, 256, 32768), 256, 0, s>>>(n, off, packed, ustart, tpre, tasks, hub_thr, chunk, hub_task,
-                                                        hub_nch, acc + 18, err);
+    uint32_t* long_rows = nullptr;
+    ALLOC(long_rows, n);
+    const EmitArgs e{n, off, packed, ustart, tpre, tasks, hub_thr, chunk, hub_task, hub_nch, acc + 18, long_rows,
+                     acc + 19, err};
+    launch_emit(e, s);
     HIPCHK(hipGetLastError());
     if (hub_thr >= 0) {
       unsigned long long hc = 0;
@@ -1208,14 +1291,14 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   p->nnz = nnz;
   p->vbase = vbase;
   p->out = d_out;
-  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr;
+  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr, *long_rows = nullptr;
   int64_t *ntask = nullptr, *tpre = nullptr, *bsum = nullptr;
   uint64_t* tasks = nullptr;
   unsigned long long* q = nullptr;
   const int64_t ntasks = nnz / 2;
-  if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 2) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
+  if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 3) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
       plan_alloc(p, &ntask, nv) || plan_alloc(p, &tpre, nv + 1) || plan_alloc(p, &bsum, nv / SCAN_B + 2) ||
-      plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks)) {
+      plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks) || plan_alloc(p, &long_rows, nv)) {
     plan_free(p);
     (void)hipGetLastError();
     return fail(TRIAD_ENOMEM, "device allocation for the batch plan failed");
@@ -1256,7 +1339,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   }
   s = cs;
   k_fill_u32<<<1, 64, 0, s>>>(p->err, 1, 0);
-  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)q, 2, 0);
+  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)q, 3, 0);  // queue counters, long rows
   k_fill_u64<<<grid_for((int64_t)G * 16, 256, 4096), 256, 0, s>>>(d_out, (int64_t)G * 16, 0);
   if (nv > 0) {
     k_rows_batch<<<grid_for(nv, 256, 65535), 256, 0, s>>>(G, nv, nnz, vbase, off, nbr, flg, grow, ustart, ntask, packed,
@@ -1264,8 +1347,8 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
     scan_excl_pre(ntask, nv, tpre, bsum, s);
     k_check_tasks<<<1, 64, 0, s>>>(tpre, nv, nnz, p->err);
     if (ntasks > 0) {
-      k_emit<<<grid_for(nv * 64, 256, 32768), 256, 0, s>>>(nv, off, packed, ustart, tpre, tasks, -1, 1, nullptr,
-                                                           nullptr, nullptr, p->err);
+      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, -1, 1, nullptr, nullptr, nullptr, long_rows, q + 2, p->err};
+      launch_emit(ea, s);
       (void)launch_census(waves, variant, a, groups, s);
     }
   }
