@@ -200,13 +200,11 @@ __global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t m, const in
 
 // --------------------------------------------------------------- task list
 
-// Task list in CSR order (and the hub list): the tasks of row u are its
-// entries above u, written as (u << 32 | local index); tasks longer than the
-// hub threshold are flagged and appended to the hub list with their chunk
-// counts. Rows with at most EMIT_SHORT
-// tasks are emitted by one lane each (k_emit_short, which lists the longer
-// rows); each longer row by a whole wavefront (k_emit_long). Hub tasks are
-// appended with one atomic per wavefront step.
+// Task list in CSR order: the tasks of row u are its entries above u, written
+// as (u << 32 | local index); tasks longer than the hub threshold are flagged.
+// Rows with at most EMIT_SHORT tasks are emitted by one lane each
+// (k_emit_short, which lists the longer rows); each longer row by a whole
+// wavefront (k_emit_long). The hub list is compacted afterwards (k_hub_list).
 constexpr int64_t EMIT_SHORT = 32;
 
 struct EmitArgs {
@@ -216,11 +214,7 @@ struct EmitArgs {
   const uint32_t* ustart;
   const int64_t* tpre;
   uint64_t* tasks;
-  int64_t hub_threshold;  // < 0: no hub list
-  int64_t chunk;
-  uint64_t* hub_task;
-  int64_t* hub_nch;
-  unsigned long long* hub_count;
+  int64_t hub_threshold;  // < 0: no hub tasks
   uint32_t* long_rows;
   unsigned long long* long_count;
   const uint32_t* err;
@@ -235,30 +229,16 @@ __device__ __forceinline__ uint64_t wave_reserve(unsigned long long* ctr, uint64
 }
 
 // One task per active lane: row u (entries from b, degree du), k = index of v
-// in the row, t = task index. All lanes of the wavefront call it together.
-__device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int lane, int64_t u, int64_t b, int64_t du,
-                                          uint32_t k, int64_t t) {
+// in the row, t = task index.
+__device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int64_t u, int64_t b, int64_t du, uint32_t k,
+                                          int64_t t) {
+  if (!act) return;
   uint64_t tk = ((uint64_t)u << 32) | k;
   if (e.hub_threshold >= 0) {
-    bool hub = false;
-    int64_t L = 0;
-    if (act) {
-      const uint32_t v = e.packed[b + k] >> 2;
-      L = du + (e.off[v + 1] - e.off[v]);
-      hub = L > e.hub_threshold;
-    }
-    const uint64_t hm = __ballot(hub);
-    if (hm) {
-      const uint64_t base = wave_reserve(e.hub_count, hm, lane);
-      if (hub) {
-        const uint64_t slot = base + (uint64_t)__popcll(hm & ((1ull << lane) - 1));
-        e.hub_task[slot] = (uint64_t)t;
-        e.hub_nch[slot] = (L + e.chunk - 1) / e.chunk;
-        tk |= HUB_BIT;
-      }
-    }
+    const uint32_t v = e.packed[b + k] >> 2;
+    if (du + (e.off[v + 1] - e.off[v]) > e.hub_threshold) tk |= HUB_BIT;
   }
-  if (act) e.tasks[t] = tk;
+  e.tasks[t] = tk;
 }
 
 __global__ void k_emit_short(EmitArgs e) {
@@ -284,8 +264,7 @@ __global__ void k_emit_short(EmitArgs e) {
       if (lng) e.long_rows[base + (uint64_t)__popcll(lm & ((1ull << lane) - 1))] = (uint32_t)u;
     }
     const int64_t mine = lng ? 0 : cnt;
-    for (int64_t j = 0; __ballot(j < mine) != 0; ++j)
-      emit_task(e, j < mine, lane, u, b, du, s + (uint32_t)j, t0 + j);
+    for (int64_t j = 0; j < mine; ++j) emit_task(e, true, u, b, du, s + (uint32_t)j, t0 + j);
   }
 }
 
@@ -302,8 +281,53 @@ __global__ void k_emit_long(EmitArgs e) {
     const int64_t cnt = du - s;
     for (int64_t i0 = 0; i0 < cnt; i0 += 64) {
       const int64_t i = i0 + lane;
-      emit_task(e, i < cnt, lane, u, b, du, s + (uint32_t)i, t0 + i);
+      emit_task(e, i < cnt, u, b, du, s + (uint32_t)i, t0 + i);
     }
+  }
+}
+
+// Hub list: the flagged tasks, compacted with one atomic per tile of HUB_TILE
+// tasks (list order is free), with the chunk count of each.
+constexpr int HUB_TILE = 256 * 16;
+__global__ void __launch_bounds__(256) k_hub_list(const uint64_t* __restrict__ tasks, int64_t ntasks,
+                                                  const int64_t* __restrict__ off, const uint32_t* __restrict__ packed,
+                                                  int64_t chunk, uint64_t* __restrict__ hub_task,
+                                                  int64_t* __restrict__ hub_nch, unsigned long long* __restrict__ hub_count,
+                                                  const uint32_t* __restrict__ err) {
+  if (*err) return;
+  __shared__ unsigned int wsum[4];
+  __shared__ unsigned long long base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t t0 = (int64_t)blockIdx.x * HUB_TILE; t0 < ntasks; t0 += (int64_t)gridDim.x * HUB_TILE) {
+    // each wavefront counts its quarter of the tile, 64 tasks per step
+    const int64_t q0 = t0 + (int64_t)w * (HUB_TILE / 4), q1 = min(q0 + HUB_TILE / 4, ntasks);
+    unsigned int c = 0;
+    for (int64_t t = q0 + lane; t - lane < q1; t += 64)
+      c += (unsigned int)__popcll(__ballot(t < q1 && (tasks[t] & HUB_BIT)));
+    if (lane == 0) wsum[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+      base = tot ? atomicAdd(hub_count, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    uint64_t slot = base;
+    for (int i = 0; i < w; ++i) slot += wsum[i];
+    for (int64_t t = q0 + lane; t - lane < q1; t += 64) {
+      const uint64_t tk = t < q1 ? tasks[t] : 0;
+      const bool hub = (tk & HUB_BIT) != 0;
+      const uint64_t m = __ballot(hub);
+      if (hub) {
+        const uint64_t h = slot + (uint64_t)__popcll(m & ((1ull << lane) - 1));
+        const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu, k = (uint32_t)tk;
+        const int64_t au = off[u], du = off[u + 1] - au;
+        const uint32_t v = packed[au + k] >> 2;
+        hub_task[h] = (uint64_t)t;
+        hub_nch[h] = (du + (off[v + 1] - off[v]) + chunk - 1) / chunk;
+      }
+      slot += (uint64_t)__popcll(m);
+    }
+    __syncthreads();
   }
 }
 
@@ -1082,9 +1106,11 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     ALLOC(hub_pre, hub_cap + 1);
     uint32_t* long_rows = nullptr;
     ALLOC(long_rows, n);
-    const EmitArgs e{n, off, packed, ustart, tpre, tasks, hub_thr, chunk, hub_task, hub_nch, acc + 18, long_rows,
-                     acc + 19, err};
+    const EmitArgs e{n, off, packed, ustart, tpre, tasks, hub_thr, long_rows, acc + 19, err};
     launch_emit(e, s);
+    if (hub_thr >= 0)
+      k_hub_list<<<grid_for(ntasks, HUB_TILE, 32768), 256, 0, s>>>(tasks, ntasks, off, packed, chunk, hub_task, hub_nch,
+                                                                   acc + 18, err);
     HIPCHK(hipGetLastError());
     if (hub_thr >= 0) {
       unsigned long long hc = 0;
@@ -1347,7 +1373,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
     scan_excl_pre(ntask, nv, tpre, bsum, s);
     k_check_tasks<<<1, 64, 0, s>>>(tpre, nv, nnz, p->err);
     if (ntasks > 0) {
-      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, -1, 1, nullptr, nullptr, nullptr, long_rows, q + 2, p->err};
+      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, -1, long_rows, q + 2, p->err};
       launch_emit(ea, s);
       (void)launch_census(waves, variant, a, groups, s);
     }
