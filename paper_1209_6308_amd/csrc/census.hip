@@ -634,7 +634,8 @@ __device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, 
 // number of ids found in both lists (per lane).
 template <int W, bool HH>
 __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
-                                                   uint32_t vq, uint64_t slice, uint32_t col, int lane) {
+                                                   uint32_t vq, uint64_t slice, uint32_t ga, uint32_t gb, uint32_t col,
+                                                   int lane) {
   constexpr uint32_t C = WaveLds<W, HH>::COLS;
   const bool sA = na <= nb;  // the short window is N(u)'s
   const uint32_t* S = sA ? L.a : L.b;
@@ -646,10 +647,7 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
   // that a bit-field extract at offset (y << 2) mod 32 finds them whatever the
   // lowest id bit of y.
   const uint32_t thrG = sA ? uq : vq;
-  const uint32_t sel0 = sA ? 2u : 0u;  // position of the flag in the table index
-  uint32_t rowtbl = 0;
-  for (uint32_t f = 1; f < 4; ++f) rowtbl |= (uint32_t)((slice >> (4u * (f << sel0))) & 15u) << (4u * f);
-  rowtbl = uni(rowtbl | rowtbl << 16);
+  const uint32_t rowtbl = sA ? gb : ga;
   uint32_t* const hcol = L.hist + col;
   const char* const Gb = (const char*)G;
   uint32_t inter = 0;
@@ -808,7 +806,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
     }
     // ---- choose and issue the next round
     const bool item_done = (ia + na >= cur.la) && (ib + nb >= cur.lb);
-    Item nxt = cur;
+    Item nxt;  // the next item; read only when item_done
     uint32_t nia = ia + na, nib = ib + nb;
     bool more = true;
     if (item_done) {
@@ -835,11 +833,15 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
         }
       }
     }
-    const uint32_t nna_ld = more ? min(nxt.la - nia, (uint32_t)W) : 0u;
-    const uint32_t nnb_ld = more ? min(nxt.lb - nib, (uint32_t)W) : 0u;
+    // the next round's windows: more of this item, or the start of the next
+    const uint32_t* const nA = item_done ? nxt.A : cur.A;
+    const uint32_t* const nB = item_done ? nxt.B : cur.B;
+    const uint32_t nla = item_done ? nxt.la : cur.la, nlb = item_done ? nxt.lb : cur.lb;
+    const uint32_t nna_ld = more ? min(nla - nia, (uint32_t)W) : 0u;
+    const uint32_t nnb_ld = more ? min(nlb - nib, (uint32_t)W) : 0u;
     wave_lds_sync();
     // ra/rb are consumed (counts done, LDS staged): refill them for the next round
-    if (more) load_round<W>(nxt.A + nia, nna_ld, nxt.B + nib, nnb_ld, lane, ra, rb);
+    if (more) load_round<W>(nA + nia, nna_ld, nB + nib, nnb_ld, lane, ra, rb);
     // ---- merge this round from LDS
     if (BAT && cur.gid != wg && cur.la + cur.lb > 0) {
       if (wg != 0xFFFFFFFFu) {
@@ -849,7 +851,8 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
       wg = cur.gid;
     }
     if (min(na, nb) <= LOP_S && max(na, nb) >= LOP_G)
-      item_inter += lopsided_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
+      item_inter += lopsided_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice,
+                                          g.cls.ga[cur.f], g.cls.gb[cur.f], col, lane);
     else
       item_inter += merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
     steps += (na + nb) / (HH ? 16 : 32) + 4;
@@ -868,7 +871,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
     }
     wave_lds_sync();
     if (!more) break;
-    cur = nxt;
+    if (item_done) cur = nxt;
     ia = nia;
     ib = nib;
     na_ld = nna_ld;

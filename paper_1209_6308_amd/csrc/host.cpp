@@ -79,6 +79,13 @@ ClassSlices class_slices() {
       s |= (uint64_t)(classify_code(f | fa << 2 | fb << 4) & 15) << (4 * idx);
     }
     cs.s[f] = s;
+    uint32_t ga = 0, gb = 0;
+    for (unsigned g = 1; g < 4; ++g) {
+      ga |= (uint32_t)((s >> (4 * g)) & 15u) << (4 * g);
+      gb |= (uint32_t)((s >> (4 * (g << 2))) & 15u) << (4 * g);
+    }
+    cs.ga[f] = ga | ga << 16;
+    cs.gb[f] = gb | gb << 16;
   }
   return cs;
 }

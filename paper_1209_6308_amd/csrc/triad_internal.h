@@ -32,7 +32,11 @@ int fail(int status, const std::string& msg);
 // class of the triad code f | fa << 2 | fb << 4 (fa = flag of w in N(u) or 0,
 // fb = flag of w in N(v) or 0).
 struct ClassSlices {
-  uint64_t s[4];
+  uint64_t s[4];  // [f_uv]: nibble fa | fb << 2 -> class
+  // [f_uv]: class of a w found in one list only, by its flag g (nibble g,
+  // nibble 0 = 0), the four nibbles repeated at bit 16: ga for N(u) only, gb
+  // for N(v) only
+  uint32_t ga[4], gb[4];
 };
 ClassSlices class_slices();
 int classify_code(unsigned code);  // 0..15, standard order
