@@ -201,7 +201,7 @@ def main():
         for other in ("plain", "heuristic", "learned"):
             if other == args.schedule:
                 continue
-            r = run(other, max(1, args.steps // 2), 1, spans=True)
+            r = run(other, args.steps, 1, spans=True)
             if r["counts"] != counts:
                 raise SystemExit(f"schedule {other} changed the census")
             sched[other] = summary(r)

@@ -63,10 +63,16 @@ enum triad_status {
   TRIAD_EDEVICE = -7        /* no usable HIP device, or a HIP runtime error */
 };
 
+/* Order of the census work queue. Whole tasks are claimed in batches of 64
+ * consecutive queue positions; a schedule keeps CSR order for the bulk of the
+ * queue (tasks of one row u share N(u) in cache) and orders its last batches
+ * (the last 1/20 of them, at least 4,096 and at most all) costliest first,
+ * binned by the batch's summed cost key. */
 enum triad_schedule {
   TRIAD_SCHED_PLAIN = 0,     /* tasks in CSR order */
-  TRIAD_SCHED_HEURISTIC = 1, /* tasks binned and ordered longest-first by d(u)+d(v) */
-  TRIAD_SCHED_LEARNED = 2    /* tasks binned and ordered by the learned cost model */
+  TRIAD_SCHED_HEURISTIC = 1, /* last batches costliest first by the sum of d(u)+d(v) */
+  TRIAD_SCHED_LEARNED = 2    /* last batches costliest first by the learned cost model's
+                                predicted cycles, summed over the batch */
 };
 
 /* Device time of each stage of one census call, in milliseconds (HIP events

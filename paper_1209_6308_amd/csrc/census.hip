@@ -203,9 +203,15 @@ __global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t m, const in
 // Task list in CSR order: the tasks of row u are its entries above u, written
 // as (u << 32 | local index); tasks longer than the hub threshold are flagged.
 // Rows with at most EMIT_SHORT tasks are emitted by one lane each
-// (k_emit_short, which lists the longer rows); each longer row by a whole
-// wavefront (k_emit_long). The hub list is compacted afterwards (k_hub_list).
+// (k_emit_short, which lists the longer rows cut into segments of at most
+// EMIT_SEG tasks); each segment by a whole wavefront (k_emit_long), so that no
+// wavefront walks a hub row of 10^5 tasks alone. The hub list is compacted
+// afterwards (k_hub_list).
 constexpr int64_t EMIT_SHORT = 32;
+constexpr int64_t EMIT_SEG = 1024;
+
+// Capacity of the segment list for a task list of ntasks tasks over n rows.
+static inline int64_t emit_seg_cap(int64_t n, int64_t ntasks) { return n + ntasks / EMIT_SEG + 1; }
 
 struct EmitArgs {
   int64_t n;
@@ -215,18 +221,10 @@ struct EmitArgs {
   const int64_t* tpre;
   uint64_t* tasks;
   int64_t hub_threshold;  // < 0: no hub tasks
-  uint32_t* long_rows;
+  uint64_t* long_segs;  // u << 32 | segment index within the row
   unsigned long long* long_count;
   const uint32_t* err;
 };
-
-// Reserves popcount(mask) slots of a global list for the lanes in mask; every
-// lane gets the first slot (wave-uniform) and adds its rank among them.
-__device__ __forceinline__ uint64_t wave_reserve(unsigned long long* ctr, uint64_t mask, int lane) {
-  uint64_t base = 0;
-  if (lane == 0) base = atomicAdd(ctr, (unsigned long long)__popcll(mask));
-  return bcast64(base, 0);
-}
 
 // One task per active lane: row u (entries from b, degree du), k = index of v
 // in the row, t = task index.
@@ -258,10 +256,18 @@ __global__ void k_emit_short(EmitArgs e) {
       cnt = du - s;
     }
     const bool lng = cnt > EMIT_SHORT;
-    const uint64_t lm = __ballot(lng);
-    if (lm) {
-      const uint64_t base = wave_reserve(e.long_count, lm, lane);
-      if (lng) e.long_rows[base + (uint64_t)__popcll(lm & ((1ull << lane) - 1))] = (uint32_t)u;
+    if (__ballot(lng)) {
+      // segments of this lane's row, placed after those of the lower lanes
+      const uint32_t ns = lng ? (uint32_t)((cnt + EMIT_SEG - 1) / EMIT_SEG) : 0u;
+      uint32_t inc = ns;
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d);
+        if (lane >= d) inc += y;
+      }
+      uint64_t base = 0;
+      if (lane == 63) base = atomicAdd(e.long_count, (unsigned long long)inc);
+      base = bcast64(base, 63) + (inc - ns);
+      for (uint32_t j = 0; j < ns; ++j) e.long_segs[base + j] = ((uint64_t)u << 32) | j;
     }
     const int64_t mine = lng ? 0 : cnt;
     for (int64_t j = 0; j < mine; ++j) emit_task(e, true, u, b, du, s + (uint32_t)j, t0 + j);
@@ -275,11 +281,12 @@ __global__ void k_emit_long(EmitArgs e) {
   const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t nl = (int64_t)*e.long_count;
   for (int64_t r = wave; r < nl; r += nwave) {
-    const int64_t u = e.long_rows[r];
+    const uint64_t sg = e.long_segs[r];
+    const int64_t u = (int64_t)(sg >> 32), j0 = (int64_t)(uint32_t)sg * EMIT_SEG;
     const int64_t b = e.off[u], du = e.off[u + 1] - b, t0 = e.tpre[u];
     const uint32_t s = e.ustart[u];
-    const int64_t cnt = du - s;
-    for (int64_t i0 = 0; i0 < cnt; i0 += 64) {
+    const int64_t cnt = min(du - s, j0 + EMIT_SEG);
+    for (int64_t i0 = j0; i0 < cnt; i0 += 64) {
       const int64_t i = i0 + lane;
       emit_task(e, i < cnt, u, b, du, s + (uint32_t)i, t0 + i);
     }
@@ -344,9 +351,9 @@ struct CensusArgs {
   int64_t n;
   const int64_t* off;
   const uint32_t* packed;
-  const uint64_t* tasks;   // the task queue (CSR order, or a schedule's order)
-  const uint64_t* htasks;  // tasks in CSR order, indexed by the hub list
-  const int64_t* order;    // optional: queue position -> CSR task index
+  const uint64_t* tasks;   // the task queue
+  const uint64_t* htasks;  // the task words the hub list indexes
+  const int64_t* order;    // optional: queue position -> index into tasks
   int64_t ntasks;
   const uint64_t* hub_task;
   const int64_t* hub_pre;  // [nhub+1] exclusive prefix of chunk counts
@@ -363,7 +370,6 @@ struct CensusArgs {
   ClassSlices cls;           // nibble idx = fa | fb << 2 -> class; idx 0 -> 0 (not counted)
 };
 
-constexpr int BATCH = 64;   // work items claimed per queue access
 constexpr int PAD = 1024;   // readable entries past the end of the packed array
 // rounds with at most LOP_S ids in one window and at least LOP_G in the other
 // take the entry-by-entry path (lopsided_round) instead of the merged walk
@@ -1048,6 +1054,8 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   if (waves != 1 && waves != 2 && waves != 4) return fail(TRIAD_EINVAL, "waves_per_group must be 1, 2 or 4");
   const int64_t chunk = o.chunk > 0 ? o.chunk : 32768;
   const int64_t hub_thr = o.hub_threshold == 0 ? 65536 : o.hub_threshold;
+  // schedule key: 0 none (CSR order), 1 d(u)+d(v), 2 the learned cost model
+  const int sched = o.schedule == TRIAD_SCHED_PLAIN ? 0 : (o.schedule == TRIAD_SCHED_LEARNED && o.model) ? 2 : 1;
   if (chunk < 256 || chunk > ((int64_t)1 << 30)) return fail(TRIAD_EINVAL, "chunk must be in [256, 2^30]");
   DeviceInfo di;
   if (int st = device_info(&di)) return st;
@@ -1085,6 +1093,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   int64_t ntasks = 0, nhub = 0;
   uint32_t errh = 0;
   uint64_t* tasks = nullptr;
+  int64_t* order = nullptr;
   uint64_t* hub_task = nullptr;
   int64_t *hub_nch = nullptr, *hub_pre = nullptr;
   if (n > 0) {
@@ -1107,10 +1116,17 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     ALLOC(hub_task, hub_cap);
     ALLOC(hub_nch, hub_cap);
     ALLOC(hub_pre, hub_cap + 1);
-    uint32_t* long_rows = nullptr;
-    ALLOC(long_rows, n);
-    const EmitArgs e{n, off, packed, ustart, tpre, tasks, hub_thr, long_rows, acc + 19, err};
+    uint64_t* long_segs = nullptr;
+    ALLOC(long_segs, emit_seg_cap(n, ntasks));
+    const EmitArgs e{n, off, packed, ustart, tpre, tasks, hub_thr, long_segs, acc + 19, err};
     launch_emit(e, s);
+    // A schedule reorders the last batches of the queue: in place, or, with
+    // per-task cycle recording, through a queue-position -> task index map
+    // that keeps the tasks (and so the cycles) in CSR order.
+    if (sched) {
+      if (o.task_cycles) ALLOC(order, ntasks);
+      if (int st = schedule_tail(sched, o.model, off, packed, tasks, ntasks, order, scratch, s)) return st;
+    }
     if (hub_thr >= 0)
       k_hub_list<<<grid_for(ntasks, HUB_TILE, 32768), 256, 0, s>>>(tasks, ntasks, off, packed, chunk, hub_task, hub_nch,
                                                                    acc + 18, err);
@@ -1125,17 +1141,6 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
       }
     }
   }
-  // A schedule reorders the task words themselves, so that the queue is read
-  // sequentially; with per-task cycle recording it is an index permutation
-  // instead, which keeps the cycles in CSR task order.
-  int64_t* order = nullptr;
-  uint64_t* perm = nullptr;
-  if (ntasks > 0 && o.schedule != TRIAD_SCHED_PLAIN) {
-    if (o.task_cycles) ALLOC(order, ntasks);
-    else ALLOC(perm, ntasks);
-    const int mode = (o.schedule == TRIAD_SCHED_LEARNED && o.model) ? 2 : 1;
-    if (int st = build_order(mode, o.model, n, off, packed, tasks, ntasks, order, perm, scratch, s)) return st;
-  }
   ev.rec(2, s);
   int groups = 0;
   if (ntasks > 0) {
@@ -1143,7 +1148,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.n = n;
     a.off = off;
     a.packed = packed;
-    a.tasks = perm ? perm : tasks;
+    a.tasks = tasks;
     a.htasks = tasks;
     a.order = order;
     a.ntasks = ntasks;
@@ -1320,14 +1325,16 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   p->nnz = nnz;
   p->vbase = vbase;
   p->out = d_out;
-  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr, *long_rows = nullptr;
+  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr;
+  uint64_t* long_segs = nullptr;
   int64_t *ntask = nullptr, *tpre = nullptr, *bsum = nullptr;
   uint64_t* tasks = nullptr;
   unsigned long long* q = nullptr;
   const int64_t ntasks = nnz / 2;
   if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 3) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
       plan_alloc(p, &ntask, nv) || plan_alloc(p, &tpre, nv + 1) || plan_alloc(p, &bsum, nv / SCAN_B + 2) ||
-      plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks) || plan_alloc(p, &long_rows, nv)) {
+      plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks) ||
+      plan_alloc(p, &long_segs, emit_seg_cap(nv, ntasks))) {
     plan_free(p);
     (void)hipGetLastError();
     return fail(TRIAD_ENOMEM, "device allocation for the batch plan failed");
@@ -1376,7 +1383,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
     scan_excl_pre(ntask, nv, tpre, bsum, s);
     k_check_tasks<<<1, 64, 0, s>>>(tpre, nv, nnz, p->err);
     if (ntasks > 0) {
-      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, -1, long_rows, q + 2, p->err};
+      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, -1, long_segs, q + 2, p->err};
       launch_emit(ea, s);
       (void)launch_census(waves, variant, a, groups, s);
     }

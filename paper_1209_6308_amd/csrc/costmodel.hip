@@ -10,6 +10,7 @@
 // min(d(u),d(v)), max(d(u),d(v)), entries of N(u) above v.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -226,59 +227,85 @@ __global__ void k_zero_f32(float* p, int64_t m) {
 
 // ---------------------------------------------------------------- schedule
 
-// Tasks are binned by cost, one bin per octave (mode 1: d(u)+d(v); mode 2: the
-// model's predicted cycles, whose log2 it outputs), and laid out costliest bin
-// first. The layout is a stable counting sort: within a bin the tasks keep
-// their CSR order, so the tasks of one vertex u stay together and its list
-// N(u) keeps being reused from L2 by neighbouring queue positions. Work is cut
-// into chunks of SCHED_CHUNK tasks, one wavefront each.
-constexpr int64_t SCHED_CHUNK = 8192;
-// Bins per octave of the cost. Finer bins order the long tasks more exactly but
-// scatter the tasks of one vertex u (whose costs differ by d(v)) over more of
-// the queue, and N(u) is then fetched from HBM more often.
-constexpr float SCHED_BPO = 1.0f;
-// The learned schedule evaluates the network only for tasks of at least this
-// many merge entries (about one LDS round); shorter ones take the lowest bin,
-// i.e. they run last, in CSR order.
-constexpr uint32_t SCHED_MLP_MIN = 512;
+// The census claims whole tasks BATCH consecutive CSR tasks at a time; in CSR
+// order, neighbouring batches share rows u and keep N(u) in cache. A schedule
+// keeps that order for the bulk of the queue and orders only its last batches
+// costliest first (longest processing time first), so that no costly batch is
+// claimed when the other wavefronts are about to run dry. Batch key: the sum
+// over its tasks of d(u)+d(v) + SCHED_TASK_OH (heuristic) or of the network's
+// predicted cycles (learned); tasks merged from the hub list add nothing. The
+// order is a stable counting sort over SCHED_BPO bins per octave of the key,
+// the first bin the costliest.
+constexpr float SCHED_BPO = 4.0f;
+// Per-task cost outside the merge, in merge entries: every task takes at
+// least one merge round.
+constexpr float SCHED_TASK_OH = 256.0f;
+// Batches per chunk of the counting sort: one wavefront each in the scatter.
+constexpr int64_t SCHED_CHUNK = 256;
 
-// Cost bin of every task (split tasks: bin 0, the census queue skips them) and
-// each chunk's count per bin, bin-major: cnt[b * nchunks + c]. The weights are
-// read at wave-uniform addresses, so they arrive through the scalar cache and
-// each multiply-add takes one VALU op.
-__global__ void __launch_bounds__(64) k_task_bins(int mode, const float* __restrict__ gw, const int64_t* __restrict__ off,
-                                                  const uint32_t* __restrict__ packed, const uint64_t* __restrict__ tasks,
-                                                  int64_t ntasks, int64_t nchunks, uint8_t* __restrict__ bin,
-                                                  unsigned int* __restrict__ cnt) {
-  __shared__ unsigned int h[SCHED_BINS];
-  const int lane = threadIdx.x;
-  const int64_t c = blockIdx.x;
-  for (int b = lane; b < SCHED_BINS; b += 64) h[b] = 0;
-  __syncthreads();
-  const int64_t t0 = c * SCHED_CHUNK, t1 = min(t0 + SCHED_CHUNK, ntasks);
-  for (int64_t t = t0 + lane; t < t1; t += 64) {
-    const uint64_t tk = tasks[t];
-    int b = 0;
-    if (!(tk & HUB_BIT)) {
-      const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu, k = (uint32_t)tk;
-      const int64_t au = off[u];
-      const uint32_t du = (uint32_t)(off[u + 1] - au);
-      const uint32_t v = packed[au + k] >> 2;
-      const uint32_t dv = (uint32_t)(off[v + 1] - off[v]);
-      if (mode != 2) {
-        b = (int)floorf(log2f((float)du + (float)dv) * SCHED_BPO);
-      } else if (du + dv >= SCHED_MLP_MIN) {
-        float x[NI];
-        task_features(du, dv, du - k - 1, x);
-        b = (int)floorf(mlp_forward(gw, x) * SCHED_BPO);
+__device__ __forceinline__ int key_bin(float key) {
+  if (!(key < 1.0e4f)) return SCHED_BINS - 1;  // also an infinite or NaN key
+  const int b = (int)floorf(key * SCHED_BPO);
+  return b < 0 ? 0 : (b >= SCHED_BINS ? SCHED_BINS - 1 : b);
+}
+
+__device__ __forceinline__ float wave_sum_f32(float x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d);
+  return x;
+}
+
+// Bin of batches from .. nbatch-1 (bin[b - from]), one wavefront per batch
+// and one lane per task. Under the learned key every lane evaluates the
+// network; the weights are read at wave-uniform addresses, through the
+// scalar cache.
+__global__ void __launch_bounds__(256) k_batch_keys(int mode, const float* __restrict__ gw,
+                                                    const int64_t* __restrict__ off, const uint32_t* __restrict__ packed,
+                                                    const uint64_t* __restrict__ tasks, int64_t ntasks, int64_t from,
+                                                    int64_t nbatch, uint8_t* __restrict__ bin) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t bt = from + wave; bt < nbatch; bt += nwave) {
+    const int64_t t = bt * BATCH + lane;
+    uint32_t du = 0, dv = 0, above = 0;
+    bool live = false;
+    if (t < ntasks) {
+      const uint64_t tk = tasks[t];
+      if (!(tk & HUB_BIT)) {
+        const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu, k = (uint32_t)tk;
+        const int64_t au = off[u];
+        du = (uint32_t)(off[u + 1] - au);
+        const uint32_t v = packed[au + k] >> 2;
+        dv = (uint32_t)(off[v + 1] - off[v]);
+        above = du - k - 1;
+        live = true;
       }
-      b = b < 0 ? 0 : (b >= SCHED_BINS ? SCHED_BINS - 1 : b);
     }
-    bin[t] = (uint8_t)b;
-    atomicAdd(&h[b], 1u);
+    float c;
+    if (mode == 2) {
+      float x[NI];
+      task_features(du, dv, above, x);
+      c = exp2f(mlp_forward(gw, x));
+    } else {
+      c = (float)du + (float)dv + SCHED_TASK_OH;
+    }
+    const float sum = wave_sum_f32(live ? c : 0.0f);
+    if (lane == 0) bin[bt - from] = (uint8_t)(sum > 0.0f ? key_bin(log2f(sum)) : 0);
   }
+}
+
+// Each chunk's count per bin, bin-major: cnt[b * nchunks + c].
+__global__ void __launch_bounds__(256) k_bin_count(const uint8_t* __restrict__ bin, int64_t m, int64_t chunk,
+                                                   int64_t nchunks, unsigned int* __restrict__ cnt) {
+  __shared__ unsigned int h[SCHED_BINS];
+  const int64_t c = blockIdx.x;
+  for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) h[b] = 0;
   __syncthreads();
-  for (int b = lane; b < SCHED_BINS; b += 64) cnt[(int64_t)b * nchunks + c] = h[b];
+  const int64_t i1 = min((c + 1) * chunk, m);
+  for (int64_t i = c * chunk + threadIdx.x; i < i1; i += blockDim.x) atomicAdd(&h[bin[i]], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) cnt[(int64_t)b * nchunks + c] = h[b];
 }
 
 // Per bin (one block each): exclusive prefix of the chunk counts, in place as
@@ -322,37 +349,32 @@ __global__ void k_bin_starts(unsigned long long* total) {
   }
 }
 
-// Stable scatter, one wavefront per chunk, 64 tasks per step: lanes holding
+// Stable scatter, one wavefront per chunk, 64 entries per step: lanes holding
 // the same bin are ranked by lane order (their bin equality mask is built
-// from one ballot per bin bit), after the chunk's earlier tasks of that bin.
-// Writes either the task words themselves in schedule order (perm) or their
-// CSR indices (order).
-__global__ void __launch_bounds__(64) k_bin_scatter(const uint8_t* __restrict__ bin, const uint64_t* __restrict__ tasks,
-                                                    int64_t ntasks, int64_t nchunks, const unsigned long long* __restrict__ pre,
-                                                    const unsigned long long* __restrict__ start, int64_t* __restrict__ order,
-                                                    uint64_t* __restrict__ perm) {
+// from one ballot per bin bit), after the chunk's earlier entries of that
+// bin. Writes idx[position] = base + entry.
+__global__ void __launch_bounds__(64) k_bin_scatter(const uint8_t* __restrict__ bin, int64_t m, int64_t chunk,
+                                                    int64_t nchunks, const unsigned long long* __restrict__ pre,
+                                                    const unsigned long long* __restrict__ start, int64_t base,
+                                                    int64_t* __restrict__ idx) {
   __shared__ unsigned long long next[SCHED_BINS];
   const int lane = threadIdx.x;
   const int64_t c = blockIdx.x;
   for (int b = lane; b < SCHED_BINS; b += 64) next[b] = start[b] + pre[(int64_t)b * nchunks + c];
   __syncthreads();
-  const int64_t t0 = c * SCHED_CHUNK, t1 = min(t0 + SCHED_CHUNK, ntasks);
+  const int64_t i0 = c * chunk, i1 = min(i0 + chunk, m);
   const uint64_t below = (1ull << lane) - 1;
-  for (int64_t s0 = t0; s0 < t1; s0 += 64) {
-    const int64_t t = s0 + lane;
-    const bool act = t < t1;
-    const uint32_t b = act ? bin[t] : (uint32_t)SCHED_BINS;  // no bin matches an idle lane
+  for (int64_t s0 = i0; s0 < i1; s0 += 64) {
+    const int64_t i = s0 + lane;
+    const bool act = i < i1;
+    const uint32_t b = act ? bin[i] : (uint32_t)SCHED_BINS;  // no bin matches an idle lane
     uint64_t eq = ~0ull;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const uint64_t m = __ballot((b >> k) & 1u);
-      eq &= ((b >> k) & 1u) ? m : ~m;
+      const uint64_t mk = __ballot((b >> k) & 1u);
+      eq &= ((b >> k) & 1u) ? mk : ~mk;
     }
-    if (act) {
-      const unsigned long long pos = next[b] + (unsigned long long)__popcll(eq & below);
-      if (perm) perm[pos] = tasks[t];
-      else order[pos] = t;
-    }
+    if (act) idx[next[b] + (unsigned long long)__popcll(eq & below)] = base + i;
     __syncthreads();
     if (act && (eq >> lane) == 1ull) next[b] += (unsigned long long)__popcll(eq);  // last lane of its group
     __syncthreads();
@@ -366,25 +388,64 @@ static int grid_of(int64_t work, int threads, int cap) {
   return (int)g;
 }
 
-int build_order(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* packed,
-                const uint64_t* tasks, int64_t ntasks, int64_t* order, uint64_t* perm, Scratch& scratch, hipStream_t s) {
-  (void)n;
-  if (ntasks <= 0) return TRIAD_OK;
-  const int64_t nchunks = (ntasks + SCHED_CHUNK - 1) / SCHED_CHUNK;
-  uint8_t* bin = nullptr;
+// idx = base + the entries 0..m-1 ordered by bin, highest bin first, stable.
+static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_t base, int64_t* idx, Scratch& scratch,
+                            hipStream_t s) {
+  const int64_t nchunks = (m + chunk - 1) / chunk;
   unsigned int* cnt = nullptr;
   unsigned long long* pre = nullptr;
   unsigned long long* start = nullptr;
-  ALLOC(bin, ntasks);
   ALLOC(cnt, nchunks * SCHED_BINS);
   ALLOC(pre, nchunks * SCHED_BINS);
   ALLOC(start, SCHED_BINS);
-  hipLaunchKernelGGL(k_task_bins, dim3((unsigned)nchunks), dim3(64), 0, s, mode, model, off, packed, tasks, ntasks, nchunks,
-                     bin, cnt);
+  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nchunks), dim3(256), 0, s, bin, m, chunk, nchunks, cnt);
   hipLaunchKernelGGL(k_bin_scan, dim3(SCHED_BINS), dim3(256), 0, s, cnt, nchunks, pre, start);
   hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, s, start);
-  hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)nchunks), dim3(64), 0, s, bin, tasks, ntasks, nchunks, pre, start, order,
-                     perm);
+  hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)nchunks), dim3(64), 0, s, bin, m, chunk, nchunks, pre, start, base,
+                     idx);
+  HIPCHK(hipGetLastError());
+  return TRIAD_OK;
+}
+
+// Queue batch from + i takes task batch border[i]: the task words moved into
+// tmp (then copied back), or the task indices written to order.
+__global__ void k_apply_batches(const int64_t* __restrict__ border, int64_t from, int64_t tail,
+                                const uint64_t* __restrict__ tasks, uint64_t* __restrict__ tmp,
+                                int64_t* __restrict__ order) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, m = tail * BATCH;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    const int64_t src = border[j / BATCH] * BATCH + (j % BATCH);
+    if (order) order[from * BATCH + j] = src;
+    else tmp[j] = tasks[src];
+  }
+}
+
+__global__ void k_iota64(int64_t* __restrict__ p, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) p[j] = j;
+}
+
+int schedule_tail(int mode, const float* model, const int64_t* off, const uint32_t* packed, uint64_t* tasks,
+                  int64_t ntasks, int64_t* order, Scratch& scratch, hipStream_t s) {
+  if (mode == 2 && !model) return fail(TRIAD_EINVAL, "learned schedule without a model");
+  if (order && ntasks > 0) hipLaunchKernelGGL(k_iota64, dim3(grid_of(ntasks, 256, 65536)), dim3(256), 0, s, order, ntasks);
+  // full batches only: a partial last batch stays last
+  const int64_t nfull = ntasks / BATCH;
+  const int64_t tail = std::min(nfull, std::max(nfull / SCHED_TAIL_DIV, SCHED_TAIL_MIN)), from = nfull - tail;
+  if (tail <= 0) return TRIAD_OK;
+  uint8_t* bin = nullptr;
+  int64_t* border = nullptr;
+  ALLOC(bin, tail);
+  ALLOC(border, tail);
+  hipLaunchKernelGGL(k_batch_keys, dim3(grid_of(tail, 4, 65536)), dim3(256), 0, s, mode, model, off, packed,
+                     (const uint64_t*)tasks, ntasks, from, nfull, bin);
+  if (int st = stable_bin_order(bin, tail, SCHED_CHUNK, from, border, scratch, s)) return st;
+  uint64_t* tmp = nullptr;
+  if (!order) ALLOC(tmp, tail * BATCH);
+  hipLaunchKernelGGL(k_apply_batches, dim3(grid_of(tail * BATCH, 256, 65536)), dim3(256), 0, s, (const int64_t*)border,
+                     from, tail, (const uint64_t*)tasks, tmp, order);
+  if (!order)
+    HIPCHK(hipMemcpyAsync(tasks + from * BATCH, tmp, sizeof(uint64_t) * tail * BATCH, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipGetLastError());
   return TRIAD_OK;
 }

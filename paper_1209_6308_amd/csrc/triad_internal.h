@@ -90,13 +90,21 @@ struct Scratch {
 // bit 63 marks a task that is split into chunks (merged from the hub list).
 constexpr uint64_t HUB_BIT = 1ull << 63;
 
-// Schedule: the tasks longest-first by a cost key binned into SCHED_BINS bins
-// (stable counting sort: CSR order within a bin). mode 1 = d(u)+d(v), mode 2 =
-// the learned model's predicted log2 cycles (model = device weights).
+// Whole tasks are claimed from the census queue BATCH consecutive tasks at a
+// time; a schedule orders these batches.
+constexpr int BATCH = 64;
+
+// Schedules: the census claims whole tasks in batches of BATCH consecutive
+// queue positions. A schedule keeps the queue in CSR order except for its last
+// max(nb / SCHED_TAIL_DIV, SCHED_TAIL_MIN) full batches (all of them if
+// fewer), which it puts costliest first by a cost key binned into SCHED_BINS
+// bins (stable counting sort: CSR order within a bin). mode 1: d(u)+d(v);
+// mode 2: the learned model's predicted log2 cycles (model = device weights).
 constexpr int SCHED_BINS = 128;
-// Exactly one of order (CSR task indices) and perm (the task words) is written,
-// in schedule order.
-int build_order(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* packed,
-                const uint64_t* tasks, int64_t ntasks, int64_t* order, uint64_t* perm, Scratch& scratch, hipStream_t s);
+constexpr int64_t SCHED_TAIL_DIV = 20, SCHED_TAIL_MIN = 4096;
+// Reorders the task list in place, or, if order is not null, leaves it and
+// writes order[queue position] = task index for all ntasks positions.
+int schedule_tail(int mode, const float* model, const int64_t* off, const uint32_t* packed, uint64_t* tasks,
+                  int64_t ntasks, int64_t* order, Scratch& scratch, hipStream_t s);
 
 }  // namespace triad

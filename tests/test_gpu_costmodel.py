@@ -77,6 +77,18 @@ def test_cycle_recording(torch):
     assert r > 0.3, r
 
 
+def test_cycle_recording_under_a_schedule(torch):
+    """With a schedule the queue is reordered, but the cycles still come back
+    indexed by CSR task: they correlate with the task's own features."""
+    g = graphs.rmat(12, 8, seed=4)
+    cyc = costmodel.record_cycles(g, hub_threshold=-1, schedule="heuristic").cpu().numpy().astype(np.int64)
+    assert cyc.size == g.nnz // 2
+    assert np.all(cyc > 0)
+    F = mlp.task_features(g.offsets, g.nbrs)
+    r = np.corrcoef(F[:, 2], np.log2(cyc))[0, 1]
+    assert r > 0.3, r
+
+
 @pytest.mark.parametrize("schedule", ["heuristic", "learned"])
 def test_schedules_exact(torch, schedule):
     g = graphs.rmat(13, 8, seed=6, recip_p=0.2)
@@ -86,9 +98,12 @@ def test_schedules_exact(torch, schedule):
     if schedule == "learned":
         w = torch.tensor(costmodel.init_weights(2), device="cuda")
         kw["model"] = w
-    for hub in (0, 64):
+    # hub 0: the default threshold; 64: a long-task list of most tasks, many
+    # of them split; -1: no hub split (the learned schedule still lists the
+    # tasks above its own threshold)
+    for hub in (0, 64, -1):
         got, st, tm = triad.triad_census_device(g.n, g.nnz, *d, schedule=schedule, hub_threshold=hub, chunk=256, **kw)
-        assert got == want
+        assert got == want, hub
 
 
 def test_wave_spans(torch):
