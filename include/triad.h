@@ -66,7 +66,7 @@ enum triad_status {
 /* Order of the census work queue. Whole tasks are claimed in batches of 64
  * consecutive queue positions; a schedule keeps CSR order for the bulk of the
  * queue (tasks of one row u share N(u) in cache) and orders its last batches
- * (the last 1/20 of them, at least 4,096 and at most all) costliest first,
+ * (the last 1/10 of them, at least 4,096 and at most all) costliest first,
  * binned by the batch's summed cost key. */
 enum triad_schedule {
   TRIAD_SCHED_PLAIN = 0,     /* tasks in CSR order */

@@ -101,7 +101,7 @@ constexpr int BATCH = 64;
 // bins (stable counting sort: CSR order within a bin). mode 1: d(u)+d(v);
 // mode 2: the learned model's predicted log2 cycles (model = device weights).
 constexpr int SCHED_BINS = 128;
-constexpr int64_t SCHED_TAIL_DIV = 20, SCHED_TAIL_MIN = 4096;
+constexpr int64_t SCHED_TAIL_DIV = 10, SCHED_TAIL_MIN = 4096;
 // Reorders the task list in place, or, if order is not null, leaves it and
 // writes order[queue position] = task index for all ntasks positions.
 int schedule_tail(int mode, const float* model, const int64_t* off, const uint32_t* packed, uint64_t* tasks,
