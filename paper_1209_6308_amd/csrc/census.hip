@@ -573,14 +573,17 @@ template <int W>
 __device__ __forceinline__ uint32_t count_le(const uint32_t* x, uint32_t n, uint32_t bound, int lane) {
   constexpr uint32_t S = W / 64;
   const uint32_t l = (uint32_t)lane;
-  const bool in = l * S < n;
   const uint32_t last = key_of(x[min(l * S + S - 1, n - 1)]);
-  const uint32_t c1 = (uint32_t)__popcll(__ballot(in && last <= bound));  // whole blocks <= bound
+  // (each ballot of one compare is that compare's lane mask as it stands;
+  // masks are combined on the scalar unit)
+  const uint32_t c1 = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(l * S < n) &
+                                         __builtin_amdgcn_ballot_w64(last <= bound));  // whole blocks <= bound
   if (c1 * S >= n) return n;
   const uint32_t e = c1 * S + l;
   const bool in2 = l < S && e < n;
   const uint32_t v = key_of(x[in2 ? e : 0]);
-  return c1 * S + (uint32_t)__popcll(__ballot(in2 && v <= bound));
+  return c1 * S + (uint32_t)__popcll(((1ull << S) - 1) & __builtin_amdgcn_ballot_w64(e < n) &
+                                     __builtin_amdgcn_ballot_w64(v <= bound));
 }
 
 // Per-lane two-pointer walk of the lane's merge-path range of one round:
@@ -655,7 +658,6 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
   const uint32_t thrG = sA ? uq : vq;
   const uint32_t rowtbl = sA ? gb : ga;
   uint32_t* const hcol = L.hist + col;
-  const char* const Gb = (const char*)G;
   uint32_t inter = 0;
   for (uint32_t t0 = 0; t0 < ns; t0 += 64) {
     const uint32_t t = t0 + (uint32_t)lane;
@@ -663,27 +665,27 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
     const uint32_t x = S[act ? t : 0];
     const uint32_t kx = x | 3u, x0 = x & ~3u;
     // lower bound of x's id in G[0, ng), ng >= 1: a packed word is below x0
-    // iff its id is below x's; the base is kept in bytes. A full window (the
-    // usual case) takes a fixed, unrolled sequence of halvings.
-    uint32_t base = 0;
+    // iff its id is below x's; the cursor is an LDS address, so each probe is
+    // a read at an immediate offset. A full window (the usual case) takes a
+    // fixed, unrolled sequence of halvings.
+    const uint32_t* p = G;
     if (ng == (uint32_t)W) {
 #pragma unroll
       for (uint32_t len = W; len > 1;) {
         const uint32_t half = len >> 1;
-        const uint32_t probe = base + half * 4u;
-        base = *(const uint32_t*)(Gb + probe) < x0 ? probe : base;
+        p = p[half] < x0 ? p + half : p;
         len -= half;
       }
     } else {
       for (uint32_t len = ng; len > 1;) {
         const uint32_t half = len >> 1;
-        const uint32_t probe = base + half * 4u;
-        base = *(const uint32_t*)(Gb + probe) < x0 ? probe : base;
+        p = p[half] < x0 ? p + half : p;
         len -= half;
       }
     }
-    const uint32_t gb = *(const uint32_t*)(Gb + base);
-    const uint32_t gr = gb < x0 ? *(const uint32_t*)(Gb + base + 4u) : gb;  // G[ng] is the sentinel
+    // both candidates in one read (G[ng] is the sentinel)
+    const uint32_t g0 = p[0], g1 = p[1];
+    const uint32_t gr = g0 < x0 ? g1 : g0;
     const bool common = act & (key_of(gr) == kx);
     const uint32_t fs = x & 3u, fg = common ? gr & 3u : 0u;
     // canonical selection (Fig. 5 step 2.1.4) for the S id
@@ -700,10 +702,13 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
   const uint32_t nfull = ng & ~63u;
   uint32_t e = (uint32_t)lane;
   if (nfull == (uint32_t)W) {
+    // all reads first: one wait instead of one per chunk
+    uint32_t y[W / 64];
+#pragma unroll
+    for (int j = 0; j < W / 64; ++j) y[j] = G[j * 64 + lane];
 #pragma unroll
     for (int j = 0; j < W / 64; ++j) {
-      const uint32_t y = G[j * 64 + lane];
-      const uint32_t off = y > thrG ? y << 2 : 0u;
+      const uint32_t off = y[j] > thrG ? y[j] << 2 : 0u;
       atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
     }
     return inter;
