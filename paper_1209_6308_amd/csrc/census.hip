@@ -698,7 +698,11 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
     if (common) atomicSub(hcol + gcls * C, 1u);
     inter += (uint32_t)common;
   }
-  // ids of G, classified as found in G only, 64 per step
+  // ids of G, classified as found in G only, 64 per step. G is sorted: if
+  // its last id is not above the threshold none is counted, if its first is
+  // every one is.
+  const uint32_t gfirst = uni(G[0]), glast = uni(G[ng - 1]);
+  if (glast <= thrG) return inter;
   const uint32_t nfull = ng & ~63u;
   uint32_t e = (uint32_t)lane;
   if (nfull == (uint32_t)W) {
@@ -706,10 +710,15 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
     uint32_t y[W / 64];
 #pragma unroll
     for (int j = 0; j < W / 64; ++j) y[j] = G[j * 64 + lane];
+    if (gfirst > thrG) {
 #pragma unroll
-    for (int j = 0; j < W / 64; ++j) {
-      const uint32_t off = y[j] > thrG ? y[j] << 2 : 0u;
-      atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
+      for (int j = 0; j < W / 64; ++j) atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, y[j] << 2, 4) * C, 1u);
+    } else {
+#pragma unroll
+      for (int j = 0; j < W / 64; ++j) {
+        const uint32_t off = y[j] > thrG ? y[j] << 2 : 0u;
+        atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
+      }
     }
     return inter;
   }
