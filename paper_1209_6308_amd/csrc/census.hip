@@ -351,6 +351,7 @@ struct CensusArgs {
   int64_t n;
   const int64_t* off;
   const uint32_t* packed;
+  const uint32_t* ustart;  // per row: entries below the row's own id
   const uint64_t* tasks;   // the task queue
   const uint64_t* htasks;  // the task words the hub list indexes
   const int64_t* order;    // optional: queue position -> index into tasks
@@ -400,10 +401,13 @@ __device__ uint32_t global_split(const uint32_t* A, uint32_t la, const uint32_t*
 
 // One batch of work items, one item per lane (lane < cnt). An item merges
 // A = packed[aoff .. aoff+la) (a range of N(u)) with B = packed[boff ..
-// boff+lb) (a range of N(v)). uf = u | kind << 30 with kind 0 = a later chunk
-// of a split task, 1 = its first chunk, 2 = a whole task; the first two kinds
-// also add their task's dyadic term dyad = n - d(u) - d(v) (Fig. 5 step
-// 2.1.3, completed by the intersection size). vf = v << 2 | f_uv.
+// boff+lb) (a range of N(v)). A starts at the first id of N(u) above u: an
+// id w < u is never counted (Fig. 5 step 2.1.4), and the intersection sizes
+// that complete the dyadic counts follow from the triangle classes
+// (k_finalize), so the ids below u are not needed.
+// uf = u | kind << 30 with kind 0 = a later chunk of a split task, 1 = its
+// first chunk, 2 = a whole task; the first two kinds also add their task's
+// dyadic term dyad = n - d(u) - d(v) (Fig. 5 step 2.1.3). vf = v << 2 | f_uv.
 struct Batch {
   int cnt;
   int64_t aoff, boff, tid;
@@ -463,15 +467,20 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
         bt.tid = (int64_t)g.hub_task[lo];
         const uint64_t tk = g.htasks[bt.tid] & ~HUB_BIT;
         const uint32_t u = (uint32_t)(tk >> 32);
-        const int64_t au = g.off[u];
-        const uint32_t dla = (uint32_t)(g.off[u + 1] - au);
-        const uint32_t pv = g.packed[au + (uint32_t)tk];
-        const int64_t bv = g.off[pv >> 2];
-        const uint32_t dlb = (uint32_t)(g.off[(pv >> 2) + 1] - bv);
+        const int64_t au0 = g.off[u];
+        const uint32_t du = (uint32_t)(g.off[u + 1] - au0);
+        const uint32_t pv = g.packed[au0 + (uint32_t)tk];
+        const int64_t bv0 = g.off[pv >> 2];
+        const uint32_t dv = (uint32_t)(g.off[(pv >> 2) + 1] - bv0);
+        // the ids of N(u) above u
+        const uint32_t su = g.ustart[u];
+        const int64_t au = au0 + su, bv = bv0;
+        const uint32_t dla = du - su, dlb = dv;
         const uint32_t* Ag = g.packed + au;
         const uint32_t* Bg = g.packed + bv;
         const uint64_t Ltot = (uint64_t)dla + dlb;
-        const uint64_t d0 = (uint64_t)c * g.chunk, d1 = min(d0 + (uint64_t)g.chunk, Ltot);
+        // the chunk count came from d(u) + d(v): trailing chunks may be empty
+        const uint64_t d0 = min((uint64_t)c * g.chunk, Ltot), d1 = min(d0 + (uint64_t)g.chunk, Ltot);
         const uint32_t i0 = global_split(Ag, dla, Bg, dlb, (uint32_t)d0);
         const uint32_t i1 = global_split(Ag, dla, Bg, dlb, (uint32_t)d1);
         uint32_t k0 = (uint32_t)d0 - i0, k1 = (uint32_t)d1 - i1;
@@ -490,17 +499,20 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
           bt.gid = g.grow[u];
           nn = g.vbase[bt.gid + 1] - g.vbase[bt.gid];
         }
-        bt.dyad = c == 0 ? (int32_t)(nn - (int64_t)dla - (int64_t)dlb) : 0;
+        bt.dyad = c == 0 ? (int32_t)(nn - (int64_t)du - (int64_t)dv) : 0;
       } else {
         bt.tid = g.order ? g.order[base + lane] : (int64_t)base + lane;
         const uint64_t tk = g.tasks[bt.tid];
         if (!(tk & HUB_BIT)) {  // hub tasks were merged in phase 0: empty item here
           const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
-          bt.aoff = g.off[u];
-          bt.la = (uint32_t)(g.off[u + 1] - bt.aoff);
-          const uint32_t pv = g.packed[bt.aoff + (uint32_t)tk];
+          const int64_t au0 = g.off[u], au1 = g.off[u + 1];
+          const uint32_t pv = g.packed[au0 + (uint32_t)tk];
           bt.boff = g.off[pv >> 2];
           bt.lb = (uint32_t)(g.off[(pv >> 2) + 1] - bt.boff);
+          // the ids of N(u) above u
+          bt.aoff = au0 + g.ustart[u];
+          bt.la = (uint32_t)(au1 - bt.aoff);
+          const uint32_t du = (uint32_t)(au1 - au0), dv = bt.lb;
           bt.uf = u | (2u << 30);
           bt.vf = pv;
           int64_t nn = g.n;
@@ -508,7 +520,7 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
             bt.gid = g.grow[u];
             nn = g.vbase[bt.gid + 1] - g.vbase[bt.gid];
           }
-          bt.dyad = (int32_t)(nn - (int64_t)bt.la - (int64_t)bt.lb);
+          bt.dyad = (int32_t)(nn - (int64_t)du - (int64_t)dv);
         }
       }
     }
@@ -572,7 +584,10 @@ __device__ __forceinline__ void load_round(const uint32_t* A, uint32_t na_ld, co
 template <int W>
 __device__ __forceinline__ uint32_t count_le(const uint32_t* x, uint32_t n, uint32_t bound, int lane) {
   constexpr uint32_t S = W / 64;
-  const uint32_t l = (uint32_t)lane;
+  // recomputed from the lane id in every round: a loop-invariant index kept
+  // live across the round loop would be spilled
+  uint32_t l = (uint32_t)lane;
+  asm volatile("" : "+v"(l));
   const uint32_t last = key_of(x[min(l * S + S - 1, n - 1)]);
   // (each ballot of one compare is that compare's lane mask as it stands;
   // masks are combined on the scalar unit)
@@ -588,10 +603,9 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t* x, uint32_t n, uint
 
 // Per-lane two-pointer walk of the lane's merge-path range of one round:
 // one distinct w per step, classified in situ from its direction bits
-// (Fig. 5 steps 2.1.4-2.1.4.2, Sec. 6). Returns the number of ids found in
-// both lists.
+// (Fig. 5 steps 2.1.4-2.1.4.2, Sec. 6).
 template <int W, bool HH>
-__device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
+__device__ __forceinline__ void merge_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
                                                 uint32_t vq, uint64_t slice, uint32_t col, int lane) {
   const uint32_t D = na + nb;
   const uint32_t d0 = (uint32_t)(((uint64_t)lane * D) >> 6), d1 = (uint32_t)(((uint64_t)(lane + 1) * D) >> 6);
@@ -604,7 +618,7 @@ __device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, 
   // an id shared by A[i-1] and B[k] was consumed with A[i-1] by a lane before
   if (i > 0 && k < nb && key_of(L.a[i - 1]) == key_of(L.b[k])) ++k;
   const uint32_t start = i + k;
-  uint32_t pos = start, steps = 0;
+  uint32_t pos = start;
   uint32_t* const hcol = L.hist + col;
   // The lane predicates are kept as wavefront masks so that their logic runs
   // on the scalar unit; the vector unit only compares, selects and adds.
@@ -626,11 +640,8 @@ __device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, 
     atomicAdd(hcol + cls * WaveLds<W, HH>::COLS, 1u);
     i += (uint32_t)ta;
     k += (uint32_t)tb;
-    ++steps;
     pos = i + k;
   }
-  // entries consumed minus distinct ids: the ids found in both lists
-  return (pos - start) - steps;
 }
 
 // A round in which one window holds few ids (S, ns of them) and the other many
@@ -639,10 +650,9 @@ __device__ __forceinline__ uint32_t merge_round(WaveLds<W, HH>& L, uint32_t na, 
 // search and is classified with both flags; every id of G is classified as
 // found in its own list only, in 64-wide chunks, and the match of an S id
 // takes that one-list count back. Counter columns can therefore dip below
-// zero between flushes; flush_wave sums them as signed values. Returns the
-// number of ids found in both lists (per lane).
+// zero between flushes; flush_wave sums them as signed values.
 template <int W, bool HH>
-__device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
+__device__ __forceinline__ void lopsided_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
                                                    uint32_t vq, uint64_t slice, uint32_t ga, uint32_t gb, uint32_t col,
                                                    int lane) {
   constexpr uint32_t C = WaveLds<W, HH>::COLS;
@@ -658,7 +668,6 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
   const uint32_t thrG = sA ? uq : vq;
   const uint32_t rowtbl = sA ? gb : ga;
   uint32_t* const hcol = L.hist + col;
-  uint32_t inter = 0;
   for (uint32_t t0 = 0; t0 < ns; t0 += 64) {
     const uint32_t t = t0 + (uint32_t)lane;
     const bool act = t < ns;
@@ -696,13 +705,12 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
     // the matched G id is counted below as found in G only: take that back
     const uint32_t gcls = (common & (kx > thrG)) ? (rowtbl >> (4u * fg)) & 15u : 0u;
     if (common) atomicSub(hcol + gcls * C, 1u);
-    inter += (uint32_t)common;
   }
   // ids of G, classified as found in G only, 64 per step. G is sorted: if
   // its last id is not above the threshold none is counted, if its first is
   // every one is.
   const uint32_t gfirst = uni(G[0]), glast = uni(G[ng - 1]);
-  if (glast <= thrG) return inter;
+  if (glast <= thrG) return;
   const uint32_t nfull = ng & ~63u;
   uint32_t e = (uint32_t)lane;
   if (nfull == (uint32_t)W) {
@@ -720,7 +728,7 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
         atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
       }
     }
-    return inter;
+    return;
   }
   for (; e < nfull; e += 64) {
     const uint32_t y = G[e];
@@ -732,7 +740,6 @@ __device__ __forceinline__ uint32_t lopsided_round(WaveLds<W, HH>& L, uint32_t n
     const uint32_t off = (e < ng) & (y > thrG) ? y << 2 : 0u;
     atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
   }
-  return inter;
 }
 
 template <int W, bool HH>
@@ -771,9 +778,8 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
     if (lane < C) L.hist[c * C + lane] = 0;
   wave_lds_sync();
   const uint32_t col = (uint32_t)(lane & (C - 1));
-  // counters 1 (012) and 2 (102) hold each lane's count of ids found in both
-  // lists, by the task's u-v dyad; the rest of those two classes, n - d(u) -
-  // d(v) per task, is added when the batch is claimed
+  // counters 1 (012) and 2 (102) receive n - d(u) - d(v) per task when the
+  // batch is claimed; the common-neighbour part is added at the end
   uint32_t steps = 0;  // bound on any counter's increments since the last flush
 
   // The pipeline starts on an empty item: its round is a no-op that is
@@ -794,7 +800,6 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   cur.tid = 0;
   uint32_t wg = 0xFFFFFFFFu;  // graph whose counters the wavefront holds (batched)
   uint32_t ia = 0, ib = 0;  // position of the current round in the item
-  uint32_t item_inter = 0;  // per lane, current item
   uint64_t t_start = CYC ? __builtin_amdgcn_s_memtime() : 0;
   uint32_t ra[W / 64], rb[W / 64];
   uint32_t na_ld = 0, nb_ld = 0;
@@ -871,14 +876,12 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
       wg = cur.gid;
     }
     if (min(na, nb) <= LOP_S && max(na, nb) >= LOP_G)
-      item_inter += lopsided_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice,
+      lopsided_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice,
                                           g.cls.ga[cur.f], g.cls.gb[cur.f], col, lane);
     else
-      item_inter += merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
+      merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
     steps += (na + nb) / (HH ? 16 : 32) + 4;
     if (item_done) {
-      atomicAdd(&L.hist[(cur.f == 3 ? 2 : 1) * C + col], item_inter);
-      item_inter = 0;
       if constexpr (CYC) {
         const uint64_t t_end = __builtin_amdgcn_s_memtime();
         if (lane == 0 && cur.kind == 2) g.cycles[cur.tid] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
@@ -903,13 +906,28 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   if (lane == 0 && g.wave_span) g.wave_span[2 * wave_id + 1] = __builtin_amdgcn_s_memrealtime();
 }
 
+// The dyadic counts (Fig. 5 step 2.1.3) need each task's number of common
+// neighbours of u and v, added to 012 or 102 by the task's dyad. Summed over
+// the tasks of each dyad kind these follow from the triangle classes: a
+// triangle is a common neighbour of each of its three edges, and its class
+// fixes how many of them are mutual (030T, 030C: none; 120D, 120U, 120C: one;
+// 210: two; 300: three).
+__device__ __forceinline__ void add_common_neighbours(uint64_t* c) {
+  const uint64_t t1 = c[11] + c[12] + c[13];
+  c[1] += 3 * (c[8] + c[9]) + 2 * t1 + c[14];
+  c[2] += t1 + 2 * c[14] + 3 * c[15];
+}
+
 __global__ void k_finalize(const unsigned long long* __restrict__ acc, uint64_t clo, uint64_t chi,
                            uint64_t* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t c[16];
+  for (int k = 0; k < 16; ++k) c[k] = acc[k];
+  add_common_neighbours(c);
   uint64_t s = 0;
-  for (int c = 1; c < 16; ++c) {
-    out[c] = acc[c];
-    s += acc[c];
+  for (int k = 1; k < 16; ++k) {
+    out[k] = c[k];
+    s += c[k];
   }
   out[0] = clo - s;
   out[16] = chi - (clo < s ? 1u : 0u);
@@ -1162,6 +1180,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.n = n;
     a.off = off;
     a.packed = packed;
+    a.ustart = ustart;
     a.tasks = tasks;
     a.htasks = tasks;
     a.order = order;
@@ -1271,8 +1290,14 @@ __global__ void k_finalize_batch(int32_t G, const int64_t* __restrict__ vbase, u
     if (a % 3 == 0) a /= 3; else if (b % 3 == 0) b /= 3; else c /= 3;
     c3 = a * b * c;
   }
+  uint64_t c[16];
+  for (int k = 0; k < 16; ++k) c[k] = gout[16 * (uint64_t)g + k];
+  add_common_neighbours(c);
   uint64_t s = 0;
-  for (int k = 1; k < 16; ++k) s += gout[16 * (uint64_t)g + k];
+  for (int k = 1; k < 16; ++k) {
+    gout[16 * (uint64_t)g + k] = c[k];
+    s += c[k];
+  }
   gout[16 * (uint64_t)g] = c3 - s;
 }
 
@@ -1357,6 +1382,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   a.n = 0;
   a.off = off;
   a.packed = packed;
+  a.ustart = ustart;
   a.tasks = tasks;
   a.htasks = tasks;
   a.order = nullptr;
