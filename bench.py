@@ -10,9 +10,11 @@ count), with the graph already resident in HBM. Prints ONE JSON line.
 
 Metric: edge-pairs merged per second (an edge-pair is one task (u,v), u < v,
 over a symmetric edge), plus the census kernel's fraction of the HBM peak
-computed from algorithmic bytes B_alg = sum over tasks of 4.25*(d(u)+d(v)) + 32
+computed from algorithmic bytes B_alg = sum over tasks of 4.25*(d+(u)+d(v)) + 32
 (4-byte id and a quarter byte of direction flags per streamed entry, plus the
-two offset pairs) = 4.25 * sum_x d(x)^2 + 32 * m_sym.
+two offset pairs; the merge reads the ids of N(u) above u, d+(u) of them, and
+all of N(v)) = 4.25 * (sum_x d+(x)^2 + sum_x d(x) d-(x)) + 32 * m_sym, d-(x) =
+d(x) - d+(x) the neighbours below x.
 """
 from __future__ import annotations
 
@@ -64,6 +66,20 @@ def cpu_baseline(g, budget_entries=6.0e10, seed=7):
     return {"value": sample.size / dt, "unit": "edge-pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"every {stride}th task of the {g.name} task list in CSR order (offset {off}): "
                       f"{sample.size} of {ntasks} tasks, {dt:.1f} s wall"}
+
+
+def list_byte_sums(d_off, d_nbr, n):
+    """(sum_x d+(x)^2, sum_x d(x) d-(x)) with d-(x) / d+(x) the neighbours of x
+    below / above x: the merged list entries of all tasks, N(u) above u
+    (d+(u) entries, in d+(u) tasks) and N(v) whole (d(v) entries, in d-(v)
+    tasks). Device-side bookkeeping, outside the timed region."""
+    import torch
+    counts = d_off[1:] - d_off[:-1]
+    rows = torch.repeat_interleave(torch.arange(n, device=d_off.device, dtype=torch.int32), counts)
+    below = torch.bincount(rows[d_nbr < rows].to(torch.int64), minlength=n).to(torch.int64)
+    del rows
+    above = counts - below
+    return int((above * above).sum().item()), int((counts * below).sum().item())
 
 
 def copy_calibration(nbytes=4 << 30, reps=3):
@@ -154,12 +170,15 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = st["m_sym"] * args.steps / wall
     kern_s = sum(main["census_ms"]) / len(main["census_ms"]) / 1e3
-    b_alg = 4.25 * st["sum_d2"] + 32.0 * st["m_sym"]
+    # algorithmic bytes of one census: per task (u, v) the ids of N(u) above u
+    # and all of N(v), 4.25 B each (id + flag), plus 32 B of offsets
+    s_above2, s_d_below = list_byte_sums(d_off, d_nbr, g.n)
+    b_alg = 4.25 * (s_above2 + s_d_below) + 32.0 * st["m_sym"]
     achieved = b_alg / kern_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "k_census", "kernel_ms": round(kern_s * 1e3, 2),
-            "algorithmic_bytes_per_launch": b_alg}
+            "algorithmic_bytes_per_launch": b_alg, "sum_dplus2": s_above2, "sum_d_dminus": s_d_below}
     tfile = os.path.join(ROOT, "profiles", f"traffic_k_census_{args.workload}.json")
     if os.path.exists(tfile):
         with open(tfile) as f:

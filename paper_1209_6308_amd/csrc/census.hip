@@ -566,15 +566,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t words_rsrc(const uint32_t* p, 
 template <int W>
 __device__ __forceinline__ void load_round(const uint32_t* A, uint32_t na_ld, const uint32_t* B, uint32_t nb_ld,
                                            int lane, uint32_t (&ra)[W / 64], uint32_t (&rb)[W / 64]) {
+  // the lane's byte offset is made opaque here, in the loop, so that the
+  // chunk offsets j * 256 go into the loads' immediate fields instead of
+  // being hoisted out of the round loop as seven live registers
+  uint32_t l4 = (uint32_t)lane * 4u;
+  asm volatile("" : "+v"(l4));
   if (na_ld) {
     const __amdgpu_buffer_rsrc_t r = words_rsrc(A, na_ld);
 #pragma unroll
-    for (int j = 0; j < W / 64; ++j) ra[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (j * 64 + lane) * 4, 0, 0);
+    for (int j = 0; j < W / 64; ++j) ra[j] = __builtin_amdgcn_raw_buffer_load_b32(r, l4 + j * 256, 0, 0);
   }
   if (nb_ld) {
     const __amdgpu_buffer_rsrc_t r = words_rsrc(B, nb_ld);
 #pragma unroll
-    for (int j = 0; j < W / 64; ++j) rb[j] = __builtin_amdgcn_raw_buffer_load_b32(r, (j * 64 + lane) * 4, 0, 0);
+    for (int j = 0; j < W / 64; ++j) rb[j] = __builtin_amdgcn_raw_buffer_load_b32(r, l4 + j * 256, 0, 0);
   }
 }
 
