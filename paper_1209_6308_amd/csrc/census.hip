@@ -1162,7 +1162,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     // that keeps the tasks (and so the cycles) in CSR order.
     if (sched) {
       if (o.task_cycles) ALLOC(order, ntasks);
-      if (int st = schedule_tail(sched, o.model, off, packed, tasks, ntasks, order, scratch, s)) return st;
+      if (int st = schedule_tail(sched, o.model, off, packed, tasks, ntasks, order, o.tail_gap, scratch, s)) return st;
     }
     if (hub_thr >= 0)
       k_hub_list<<<grid_for(ntasks, HUB_TILE, 32768), 256, 0, s>>>(tasks, ntasks, off, packed, chunk, hub_task, hub_nch,

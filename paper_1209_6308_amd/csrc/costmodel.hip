@@ -242,6 +242,13 @@ constexpr float SCHED_BPO = 4.0f;
 constexpr float SCHED_TASK_OH = 256.0f;
 // Batches per chunk of the counting sort: one wavefront each in the scatter.
 constexpr int64_t SCHED_CHUNK = 256;
+// The reordering pays only when CSR order would leave a costly batch among
+// the last ones claimed (about one per wavefront): a batch among the last
+// SCHED_TAIL_LAST predicted to cost SCHED_TAIL_GAP bins (a factor
+// 2^(GAP / SCHED_BPO)) above the stretch's median batch. Otherwise the queue
+// keeps its CSR order, and with it the reuse of N(u) across batches.
+constexpr int64_t SCHED_TAIL_LAST = 8192;
+constexpr int SCHED_TAIL_GAP = 8;
 
 __device__ __forceinline__ int key_bin(float key) {
   if (!(key < 1.0e4f)) return SCHED_BINS - 1;  // also an infinite or NaN key
@@ -338,6 +345,30 @@ __global__ void __launch_bounds__(256) k_bin_scan(const unsigned int* __restrict
   }
 }
 
+// skip[0] = 1 when no batch among the last `last` of bin[0, m) is gap bins
+// or more above the median bin (total[b] = entries of bin b). One block.
+__global__ void __launch_bounds__(256) k_tail_decide(const uint8_t* __restrict__ bin, int64_t m, int64_t last,
+                                                     const unsigned long long* __restrict__ total, int gap,
+                                                     uint32_t* __restrict__ skip) {
+  __shared__ uint32_t part[256];
+  uint32_t mx = 0;
+  for (int64_t i = (m > last ? m - last : 0) + threadIdx.x; i < m; i += blockDim.x) mx = max(mx, (uint32_t)bin[i]);
+  part[threadIdx.x] = mx;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int t = 1; t < (int)blockDim.x; ++t) mx = max(mx, part[t]);
+  unsigned long long run = 0;
+  int med = 0;
+  for (int b = 0; b < SCHED_BINS; ++b) {
+    run += total[b];
+    if (2 * run >= (unsigned long long)m) {
+      med = b;
+      break;
+    }
+  }
+  skip[0] = gap >= 0 && (int)mx < med + gap ? 1u : 0u;
+}
+
 // Start of each bin in the costliest-first layout.
 __global__ void k_bin_starts(unsigned long long* total) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -356,7 +387,8 @@ __global__ void k_bin_starts(unsigned long long* total) {
 __global__ void __launch_bounds__(64) k_bin_scatter(const uint8_t* __restrict__ bin, int64_t m, int64_t chunk,
                                                     int64_t nchunks, const unsigned long long* __restrict__ pre,
                                                     const unsigned long long* __restrict__ start, int64_t base,
-                                                    int64_t* __restrict__ idx) {
+                                                    int64_t* __restrict__ idx, const uint32_t* __restrict__ skip) {
+  if (skip && *skip) return;  // the whole block leaves together
   __shared__ unsigned long long next[SCHED_BINS];
   const int lane = threadIdx.x;
   const int64_t c = blockIdx.x;
@@ -388,9 +420,10 @@ static int grid_of(int64_t work, int threads, int cap) {
   return (int)g;
 }
 
-// idx = base + the entries 0..m-1 ordered by bin, highest bin first, stable.
-static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_t base, int64_t* idx, Scratch& scratch,
-                            hipStream_t s) {
+// idx = base + the entries 0..m-1 ordered by bin, highest bin first, stable;
+// with skip given, first decides (k_tail_decide) whether to order at all.
+static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_t base, int64_t* idx, int gap,
+                            uint32_t* skip, Scratch& scratch, hipStream_t s) {
   const int64_t nchunks = (m + chunk - 1) / chunk;
   unsigned int* cnt = nullptr;
   unsigned long long* pre = nullptr;
@@ -400,9 +433,12 @@ static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_
   ALLOC(start, SCHED_BINS);
   hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nchunks), dim3(256), 0, s, bin, m, chunk, nchunks, cnt);
   hipLaunchKernelGGL(k_bin_scan, dim3(SCHED_BINS), dim3(256), 0, s, cnt, nchunks, pre, start);
+  if (skip)
+    hipLaunchKernelGGL(k_tail_decide, dim3(1), dim3(256), 0, s, bin, m, SCHED_TAIL_LAST,
+                       (const unsigned long long*)start, gap, skip);
   hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, s, start);
   hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)nchunks), dim3(64), 0, s, bin, m, chunk, nchunks, pre, start, base,
-                     idx);
+                     idx, (const uint32_t*)skip);
   HIPCHK(hipGetLastError());
   return TRIAD_OK;
 }
@@ -411,7 +447,8 @@ static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_
 // tmp (then copied back), or the task indices written to order.
 __global__ void k_apply_batches(const int64_t* __restrict__ border, int64_t from, int64_t tail,
                                 const uint64_t* __restrict__ tasks, uint64_t* __restrict__ tmp,
-                                int64_t* __restrict__ order) {
+                                int64_t* __restrict__ order, const uint32_t* __restrict__ skip) {
+  if (*skip) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x, m = tail * BATCH;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
     const int64_t src = border[j / BATCH] * BATCH + (j % BATCH);
@@ -420,13 +457,20 @@ __global__ void k_apply_batches(const int64_t* __restrict__ border, int64_t from
   }
 }
 
+__global__ void k_copy_back(const uint64_t* __restrict__ tmp, int64_t m, uint64_t* __restrict__ dst,
+                            const uint32_t* __restrict__ skip) {
+  if (*skip) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) dst[j] = tmp[j];
+}
+
 __global__ void k_iota64(int64_t* __restrict__ p, int64_t m) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) p[j] = j;
 }
 
 int schedule_tail(int mode, const float* model, const int64_t* off, const uint32_t* packed, uint64_t* tasks,
-                  int64_t ntasks, int64_t* order, Scratch& scratch, hipStream_t s) {
+                  int64_t ntasks, int64_t* order, int32_t tail_gap, Scratch& scratch, hipStream_t s) {
   if (mode == 2 && !model) return fail(TRIAD_EINVAL, "learned schedule without a model");
   if (order && ntasks > 0) hipLaunchKernelGGL(k_iota64, dim3(grid_of(ntasks, 256, 65536)), dim3(256), 0, s, order, ntasks);
   // full batches only: a partial last batch stays last
@@ -435,17 +479,21 @@ int schedule_tail(int mode, const float* model, const int64_t* off, const uint32
   if (tail <= 0) return TRIAD_OK;
   uint8_t* bin = nullptr;
   int64_t* border = nullptr;
+  uint32_t* skip = nullptr;
   ALLOC(bin, tail);
   ALLOC(border, tail);
+  ALLOC(skip, 1);
   hipLaunchKernelGGL(k_batch_keys, dim3(grid_of(tail, 4, 65536)), dim3(256), 0, s, mode, model, off, packed,
                      (const uint64_t*)tasks, ntasks, from, nfull, bin);
-  if (int st = stable_bin_order(bin, tail, SCHED_CHUNK, from, border, scratch, s)) return st;
+  const int gap = tail_gap == 0 ? SCHED_TAIL_GAP : (tail_gap < 0 ? -1 : tail_gap);
+  if (int st = stable_bin_order(bin, tail, SCHED_CHUNK, from, border, gap, skip, scratch, s)) return st;
   uint64_t* tmp = nullptr;
   if (!order) ALLOC(tmp, tail * BATCH);
   hipLaunchKernelGGL(k_apply_batches, dim3(grid_of(tail * BATCH, 256, 65536)), dim3(256), 0, s, (const int64_t*)border,
-                     from, tail, (const uint64_t*)tasks, tmp, order);
+                     from, tail, (const uint64_t*)tasks, tmp, order, (const uint32_t*)skip);
   if (!order)
-    HIPCHK(hipMemcpyAsync(tasks + from * BATCH, tmp, sizeof(uint64_t) * tail * BATCH, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_copy_back, dim3(grid_of(tail * BATCH, 256, 65536)), dim3(256), 0, s, (const uint64_t*)tmp,
+                       tail * BATCH, tasks + from * BATCH, (const uint32_t*)skip);
   HIPCHK(hipGetLastError());
   return TRIAD_OK;
 }

@@ -103,8 +103,11 @@ constexpr int BATCH = 64;
 constexpr int SCHED_BINS = 128;
 constexpr int64_t SCHED_TAIL_DIV = 10, SCHED_TAIL_MIN = 4096;
 // Reorders the task list in place, or, if order is not null, leaves it and
-// writes order[queue position] = task index for all ntasks positions.
+// writes order[queue position] = task index for all ntasks positions. The
+// reordering happens only when a batch among the last SCHED_TAIL_LAST is
+// predicted to cost 2^(gap/4) times the stretch's median batch (gap =
+// tail_gap, 0: SCHED_TAIL_GAP; < 0: always).
 int schedule_tail(int mode, const float* model, const int64_t* off, const uint32_t* packed, uint64_t* tasks,
-                  int64_t ntasks, int64_t* order, Scratch& scratch, hipStream_t s);
+                  int64_t ntasks, int64_t* order, int32_t tail_gap, Scratch& scratch, hipStream_t s);
 
 }  // namespace triad
