@@ -67,8 +67,9 @@ enum triad_status {
  * consecutive queue positions; a schedule keeps CSR order for the bulk of the
  * queue (tasks of one row u share N(u) in cache) and orders its last batches
  * (the last 1/10 of them, at least 4,096 and at most all) costliest first,
- * binned by the batch's summed cost key, when the keys predict a costly batch
- * at the very end (see triad_opts.tail_gap); otherwise CSR order stays. */
+ * binned by the batch's summed cost key, when the keys predict a batch at the
+ * very end costly enough to delay the census (see triad_opts.tail_share);
+ * otherwise CSR order stays. */
 enum triad_schedule {
   TRIAD_SCHED_PLAIN = 0,     /* tasks in CSR order */
   TRIAD_SCHED_HEURISTIC = 1, /* last batches costliest first by the sum of d(u)+d(v) */
@@ -110,10 +111,11 @@ typedef struct triad_opts {
                               (s_memrealtime, 100 MHz) at each census wavefront's
                               start and end; size it with timing->waves of a
                               previous call or grid_groups * waves_per_group */
-  int32_t tail_gap;        /* schedules: the last batches are reordered only when one
-                              of the last 8,192 is predicted to cost at least
-                              2^(tail_gap/4) times the reordered stretch's median
-                              batch; 0 = default (8, i.e. 4x), < 0 = always */
+  int32_t tail_share;      /* schedules: the last batches are reordered only when one
+                              of the last 8,192 is predicted to cost more than the
+                              mean of the last 32,768 by tail_share / 10,000 of one
+                              wavefront's share of the whole census; 0 = default
+                              (30, i.e. 0.3%), < 0 = always */
 } triad_opts;
 
 /* Census of one graph given by HOST pointers (copied to the device; the call

@@ -1162,7 +1162,10 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     // that keeps the tasks (and so the cycles) in CSR order.
     if (sched) {
       if (o.task_cycles) ALLOC(order, ntasks);
-      if (int st = schedule_tail(sched, o.model, off, packed, tasks, ntasks, order, o.tail_gap, scratch, s)) return st;
+      const int64_t nwaves = (int64_t)census_groups(waves, variant, o.task_cycles ? 1 : 0, o.grid_groups) * waves;
+      if (int st = schedule_tail(sched, o.model, n, off, ustart, packed, tasks, ntasks, order, o.tail_share, nwaves,
+                                 scratch, s))
+        return st;
     }
     if (hub_thr >= 0)
       k_hub_list<<<grid_for(ntasks, HUB_TILE, 32768), 256, 0, s>>>(tasks, ntasks, off, packed, chunk, hub_task, hub_nch,

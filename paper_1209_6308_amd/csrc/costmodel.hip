@@ -242,13 +242,18 @@ constexpr float SCHED_BPO = 4.0f;
 constexpr float SCHED_TASK_OH = 256.0f;
 // Batches per chunk of the counting sort: one wavefront each in the scatter.
 constexpr int64_t SCHED_CHUNK = 256;
-// The reordering pays only when CSR order would leave a costly batch among
-// the last ones claimed (about one per wavefront): a batch among the last
-// SCHED_TAIL_LAST predicted to cost SCHED_TAIL_GAP bins (a factor
-// 2^(GAP / SCHED_BPO)) above the stretch's median batch. Otherwise the queue
-// keeps its CSR order, and with it the reuse of N(u) across batches.
-constexpr int64_t SCHED_TAIL_LAST = 8192;
-constexpr int SCHED_TAIL_GAP = 8;
+// The reordering pays only when CSR order would leave a batch among the last
+// ones claimed (about one per wavefront) costly enough to delay the whole
+// census: one of the last SCHED_TAIL_LAST predicted to cost more than the
+// mean of the last SCHED_TAIL_SAMPLE by SCHED_TAIL_SHARE / 10,000 of one
+// wavefront's share of the census. The share is the total of d(u)+d(v)+256
+// over all tasks, per wavefront, converted to the key's units by the ratio of
+// the two sums over the sample. Only the sample is keyed first; the rest of
+// the stretch is keyed and the stretch reordered only when the test says so.
+// Otherwise the queue keeps its CSR order, and with it the reuse of N(u)
+// across batches.
+constexpr int64_t SCHED_TAIL_LAST = 8192, SCHED_TAIL_SAMPLE = 32768;
+constexpr int SCHED_TAIL_SHARE = 30;
 
 __device__ __forceinline__ int key_bin(float key) {
   if (!(key < 1.0e4f)) return SCHED_BINS - 1;  // also an infinite or NaN key
@@ -263,13 +268,17 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
 }
 
 // Bin of batches from .. nbatch-1 (bin[b - from]), one wavefront per batch
-// and one lane per task. Under the learned key every lane evaluates the
-// network; the weights are read at wave-uniform addresses, through the
-// scalar cache.
+// and one lane per task; with kval given, also the batch's key sum and its
+// sum of d(u)+d(v)+SCHED_TASK_OH (lval). Under the learned key every lane
+// evaluates the network; the weights are read at wave-uniform addresses,
+// through the scalar cache.
 __global__ void __launch_bounds__(256) k_batch_keys(int mode, const float* __restrict__ gw,
                                                     const int64_t* __restrict__ off, const uint32_t* __restrict__ packed,
                                                     const uint64_t* __restrict__ tasks, int64_t ntasks, int64_t from,
-                                                    int64_t nbatch, uint8_t* __restrict__ bin) {
+                                                    int64_t nbatch, uint8_t* __restrict__ bin,
+                                                    float* __restrict__ kval, float* __restrict__ lval,
+                                                    const uint32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -289,22 +298,30 @@ __global__ void __launch_bounds__(256) k_batch_keys(int mode, const float* __res
         live = true;
       }
     }
-    float c;
+    const float len = (float)du + (float)dv + SCHED_TASK_OH;
+    float c = len;
     if (mode == 2) {
       float x[NI];
       task_features(du, dv, above, x);
       c = exp2f(mlp_forward(gw, x));
-    } else {
-      c = (float)du + (float)dv + SCHED_TASK_OH;
     }
     const float sum = wave_sum_f32(live ? c : 0.0f);
+    if (kval) {
+      const float lsum = wave_sum_f32(live ? len : 0.0f);
+      if (lane == 0) {
+        kval[bt - from] = sum;
+        lval[bt - from] = lsum;
+      }
+    }
     if (lane == 0) bin[bt - from] = (uint8_t)(sum > 0.0f ? key_bin(log2f(sum)) : 0);
   }
 }
 
 // Each chunk's count per bin, bin-major: cnt[b * nchunks + c].
 __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* __restrict__ bin, int64_t m, int64_t chunk,
-                                                   int64_t nchunks, unsigned int* __restrict__ cnt) {
+                                                   int64_t nchunks, unsigned int* __restrict__ cnt,
+                                                   const uint32_t* __restrict__ skip) {
+  if (skip && *skip) return;  // the bins were not all written
   __shared__ unsigned int h[SCHED_BINS];
   const int64_t c = blockIdx.x;
   for (int b = threadIdx.x; b < SCHED_BINS; b += blockDim.x) h[b] = 0;
@@ -318,7 +335,9 @@ __global__ void __launch_bounds__(256) k_bin_count(const uint8_t* __restrict__ b
 // Per bin (one block each): exclusive prefix of the chunk counts, in place as
 // 64-bit offsets within the bin, and the bin's total.
 __global__ void __launch_bounds__(256) k_bin_scan(const unsigned int* __restrict__ cnt, int64_t nchunks,
-                                                  unsigned long long* __restrict__ pre, unsigned long long* __restrict__ total) {
+                                                  unsigned long long* __restrict__ pre, unsigned long long* __restrict__ total,
+                                                  const uint32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ unsigned long long part[256];
   const int b = blockIdx.x, t = threadIdx.x;
   const int64_t per = (nchunks + 255) / 256, lo = min((int64_t)t * per, nchunks), hi = min(lo + per, nchunks);
@@ -345,33 +364,63 @@ __global__ void __launch_bounds__(256) k_bin_scan(const unsigned int* __restrict
   }
 }
 
-// skip[0] = 1 when no batch among the last `last` of bin[0, m) is gap bins
-// or more above the median bin (total[b] = entries of bin b). One block.
-__global__ void __launch_bounds__(256) k_tail_decide(const uint8_t* __restrict__ bin, int64_t m, int64_t last,
-                                                     const unsigned long long* __restrict__ total, int gap,
+// Per block of rows: sum over rows u of d+(u)^2 + d(u) d-(u) (d- = ustart,
+// d+ = d - d-), i.e. the summed merge length d+(u) + d(v) of all tasks.
+__global__ void __launch_bounds__(256) k_list_sums(int64_t n, const int64_t* __restrict__ off,
+                                                   const uint32_t* __restrict__ ustart,
+                                                   unsigned long long* __restrict__ part) {
+  __shared__ unsigned long long red[256];
+  unsigned long long acc = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    const unsigned long long d = (unsigned long long)(off[u + 1] - off[u]), dm = ustart[u], dp = d - dm;
+    acc += dp * dp + d * dm;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// skip[0] = 1 unless a batch among the last `last` of the sample kval[0, m)
+// exceeds the sample mean by share / 10,000 of one wavefront's share of the
+// census (share < 0: never skip). One block.
+__global__ void __launch_bounds__(256) k_tail_decide(const float* __restrict__ kval, const float* __restrict__ lval,
+                                                     int64_t m, int64_t last, const unsigned long long* __restrict__ part,
+                                                     int nparts, int64_t ntasks, int64_t nwaves, int share,
                                                      uint32_t* __restrict__ skip) {
-  __shared__ uint32_t part[256];
-  uint32_t mx = 0;
-  for (int64_t i = (m > last ? m - last : 0) + threadIdx.x; i < m; i += blockDim.x) mx = max(mx, (uint32_t)bin[i]);
-  part[threadIdx.x] = mx;
+  __shared__ double rk[256], rl[256];
+  __shared__ float rm[256];
+  double sk = 0.0, sl = 0.0;
+  float mx = 0.0f;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    sk += kval[i];
+    sl += lval[i];
+    if (i >= m - last) mx = fmaxf(mx, kval[i]);
+  }
+  rk[threadIdx.x] = sk;
+  rl[threadIdx.x] = sl;
+  rm[threadIdx.x] = mx;
   __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int t = 1; t < (int)blockDim.x; ++t) mx = max(mx, part[t]);
-  unsigned long long run = 0;
-  int med = 0;
-  for (int b = 0; b < SCHED_BINS; ++b) {
-    run += total[b];
-    if (2 * run >= (unsigned long long)m) {
-      med = b;
-      break;
-    }
+  for (int t = 1; t < (int)blockDim.x; ++t) {
+    sk += rk[t];
+    sl += rl[t];
+    mx = fmaxf(mx, rm[t]);
   }
-  skip[0] = gap >= 0 && (int)mx < med + gap ? 1u : 0u;
+  unsigned long long total_len = 0;
+  for (int b = 0; b < nparts; ++b) total_len += part[b];
+  const double census = ((double)total_len + (double)SCHED_TASK_OH * (double)ntasks) * (sl > 0.0 ? sk / sl : 1.0);
+  const double budget = (double)share * 1e-4 * census / (double)(nwaves > 0 ? nwaves : 1);
+  skip[0] = share >= 0 && (double)mx - sk / (double)(m > 0 ? m : 1) <= budget ? 1u : 0u;
 }
 
 // Start of each bin in the costliest-first layout.
-__global__ void k_bin_starts(unsigned long long* total) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void k_bin_starts(unsigned long long* total, const uint32_t* __restrict__ skip) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || (skip && *skip)) return;
   unsigned long long run = 0;
   for (int b = SCHED_BINS - 1; b >= 0; --b) {
     const unsigned long long c = total[b];
@@ -420,10 +469,10 @@ static int grid_of(int64_t work, int threads, int cap) {
   return (int)g;
 }
 
-// idx = base + the entries 0..m-1 ordered by bin, highest bin first, stable;
-// with skip given, first decides (k_tail_decide) whether to order at all.
-static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_t base, int64_t* idx, int gap,
-                            uint32_t* skip, Scratch& scratch, hipStream_t s) {
+// idx = base + the entries 0..m-1 ordered by bin, highest bin first, stable
+// (nothing is written when *skip is set).
+static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_t base, int64_t* idx,
+                            const uint32_t* skip, Scratch& scratch, hipStream_t s) {
   const int64_t nchunks = (m + chunk - 1) / chunk;
   unsigned int* cnt = nullptr;
   unsigned long long* pre = nullptr;
@@ -431,14 +480,11 @@ static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_
   ALLOC(cnt, nchunks * SCHED_BINS);
   ALLOC(pre, nchunks * SCHED_BINS);
   ALLOC(start, SCHED_BINS);
-  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nchunks), dim3(256), 0, s, bin, m, chunk, nchunks, cnt);
-  hipLaunchKernelGGL(k_bin_scan, dim3(SCHED_BINS), dim3(256), 0, s, cnt, nchunks, pre, start);
-  if (skip)
-    hipLaunchKernelGGL(k_tail_decide, dim3(1), dim3(256), 0, s, bin, m, SCHED_TAIL_LAST,
-                       (const unsigned long long*)start, gap, skip);
-  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, s, start);
+  hipLaunchKernelGGL(k_bin_count, dim3((unsigned)nchunks), dim3(256), 0, s, bin, m, chunk, nchunks, cnt, skip);
+  hipLaunchKernelGGL(k_bin_scan, dim3(SCHED_BINS), dim3(256), 0, s, cnt, nchunks, pre, start, skip);
+  hipLaunchKernelGGL(k_bin_starts, dim3(1), dim3(64), 0, s, start, skip);
   hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)nchunks), dim3(64), 0, s, bin, m, chunk, nchunks, pre, start, base,
-                     idx, (const uint32_t*)skip);
+                     idx, skip);
   HIPCHK(hipGetLastError());
   return TRIAD_OK;
 }
@@ -469,8 +515,9 @@ __global__ void k_iota64(int64_t* __restrict__ p, int64_t m) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) p[j] = j;
 }
 
-int schedule_tail(int mode, const float* model, const int64_t* off, const uint32_t* packed, uint64_t* tasks,
-                  int64_t ntasks, int64_t* order, int32_t tail_gap, Scratch& scratch, hipStream_t s) {
+int schedule_tail(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* ustart,
+                  const uint32_t* packed, uint64_t* tasks, int64_t ntasks, int64_t* order, int32_t tail_share,
+                  int64_t nwaves, Scratch& scratch, hipStream_t s) {
   if (mode == 2 && !model) return fail(TRIAD_EINVAL, "learned schedule without a model");
   if (order && ntasks > 0) hipLaunchKernelGGL(k_iota64, dim3(grid_of(ntasks, 256, 65536)), dim3(256), 0, s, order, ntasks);
   // full batches only: a partial last batch stays last
@@ -483,10 +530,26 @@ int schedule_tail(int mode, const float* model, const int64_t* off, const uint32
   ALLOC(bin, tail);
   ALLOC(border, tail);
   ALLOC(skip, 1);
-  hipLaunchKernelGGL(k_batch_keys, dim3(grid_of(tail, 4, 65536)), dim3(256), 0, s, mode, model, off, packed,
-                     (const uint64_t*)tasks, ntasks, from, nfull, bin);
-  const int gap = tail_gap == 0 ? SCHED_TAIL_GAP : (tail_gap < 0 ? -1 : tail_gap);
-  if (int st = stable_bin_order(bin, tail, SCHED_CHUNK, from, border, gap, skip, scratch, s)) return st;
+  // key the last batches, decide, then key the rest of the stretch if needed
+  const int64_t ns = std::min(tail, SCHED_TAIL_SAMPLE);
+  const int share = tail_share == 0 ? SCHED_TAIL_SHARE : (tail_share < 0 ? -1 : tail_share);
+  constexpr int NPARTS = 1024;
+  float *kval = nullptr, *lval = nullptr;
+  unsigned long long* part = nullptr;
+  ALLOC(kval, ns);
+  ALLOC(lval, ns);
+  ALLOC(part, NPARTS);
+  hipLaunchKernelGGL(k_list_sums, dim3(NPARTS), dim3(256), 0, s, n, off, ustart, part);
+  hipLaunchKernelGGL(k_batch_keys, dim3(grid_of(ns, 4, 65536)), dim3(256), 0, s, mode, model, off, packed,
+                     (const uint64_t*)tasks, ntasks, nfull - ns, nfull, bin + (tail - ns), kval, lval,
+                     (const uint32_t*)nullptr);
+  hipLaunchKernelGGL(k_tail_decide, dim3(1), dim3(256), 0, s, (const float*)kval, (const float*)lval, ns,
+                     SCHED_TAIL_LAST, (const unsigned long long*)part, NPARTS, ntasks, nwaves, share, skip);
+  if (tail > ns)
+    hipLaunchKernelGGL(k_batch_keys, dim3(grid_of(tail - ns, 4, 65536)), dim3(256), 0, s, mode, model, off, packed,
+                       (const uint64_t*)tasks, ntasks, from, nfull - ns, bin, (float*)nullptr, (float*)nullptr,
+                       (const uint32_t*)skip);
+  if (int st = stable_bin_order(bin, tail, SCHED_CHUNK, from, border, skip, scratch, s)) return st;
   uint64_t* tmp = nullptr;
   if (!order) ALLOC(tmp, tail * BATCH);
   hipLaunchKernelGGL(k_apply_batches, dim3(grid_of(tail * BATCH, 256, 65536)), dim3(256), 0, s, (const int64_t*)border,

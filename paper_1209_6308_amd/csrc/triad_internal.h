@@ -104,10 +104,12 @@ constexpr int SCHED_BINS = 128;
 constexpr int64_t SCHED_TAIL_DIV = 10, SCHED_TAIL_MIN = 4096;
 // Reorders the task list in place, or, if order is not null, leaves it and
 // writes order[queue position] = task index for all ntasks positions. The
-// reordering happens only when a batch among the last SCHED_TAIL_LAST is
-// predicted to cost 2^(gap/4) times the stretch's median batch (gap =
-// tail_gap, 0: SCHED_TAIL_GAP; < 0: always).
-int schedule_tail(int mode, const float* model, const int64_t* off, const uint32_t* packed, uint64_t* tasks,
-                  int64_t ntasks, int64_t* order, int32_t tail_gap, Scratch& scratch, hipStream_t s);
+// reordering happens only when a batch among the last 8,192 is predicted to
+// cost more than the mean of the last 32,768 by tail_share / 10,000 (0: the
+// default 30; < 0: always) of one wavefront's share of the whole census, the
+// census running on nwaves wavefronts; ustart[u] = ids of row u below u.
+int schedule_tail(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* ustart,
+                  const uint32_t* packed, uint64_t* tasks, int64_t ntasks, int64_t* order, int32_t tail_share,
+                  int64_t nwaves, Scratch& scratch, hipStream_t s);
 
 }  // namespace triad

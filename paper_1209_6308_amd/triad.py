@@ -61,7 +61,7 @@ class Opts(ctypes.Structure):
                 ("chunk", ctypes.c_int64), ("model", ctypes.c_void_p), ("task_cycles", ctypes.c_void_p),
                 ("timing", ctypes.POINTER(Timing)), ("waves_per_group", ctypes.c_int32),
                 ("grid_groups", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
-                ("wave_span", ctypes.c_void_p), ("tail_gap", ctypes.c_int32)]
+                ("wave_span", ctypes.c_void_p), ("tail_share", ctypes.c_int32)]
 
 
 _LIB = None
@@ -134,7 +134,7 @@ def _stream(stream=None):
 
 
 def make_opts(schedule="plain", validate=0, hub_threshold=0, chunk=0, model=None, task_cycles=None,
-              waves_per_group=0, grid_groups=0, timing=None, wave_span=None, kernel_variant=0, tail_gap=0):
+              waves_per_group=0, grid_groups=0, timing=None, wave_span=None, kernel_variant=0, tail_share=0):
     o = Opts()
     o.schedule = SCHED[schedule] if isinstance(schedule, str) else int(schedule)
     o.validate = validate
@@ -146,7 +146,7 @@ def make_opts(schedule="plain", validate=0, hub_threshold=0, chunk=0, model=None
     o.grid_groups = grid_groups
     o.kernel_variant = kernel_variant
     o.wave_span = wave_span.data_ptr() if wave_span is not None else None
-    o.tail_gap = tail_gap
+    o.tail_share = tail_share
     if timing is not None:
         o.timing = ctypes.pointer(timing)
     return o

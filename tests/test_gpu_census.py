@@ -206,6 +206,6 @@ def test_full_size_golden(torch_cuda, name):
     assert g.content_hash() == rec["content_hash"]
     d = triad.to_device(g, "cuda")
     w = torch.tensor(costmodel.init_weights(2), device="cuda")
-    for sched, kw in (("plain", {}), ("heuristic", {}), ("learned", {"model": w, "tail_gap": -1})):
+    for sched, kw in (("plain", {}), ("heuristic", {}), ("learned", {"model": w, "tail_share": -1})):
         got, st, tm = triad.triad_census_device(g.n, g.nnz, *d, schedule=sched, **kw)
         assert [str(x) for x in got] == rec["census"], sched

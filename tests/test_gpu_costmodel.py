@@ -81,7 +81,7 @@ def test_cycle_recording_under_a_schedule(torch):
     """With a schedule the queue is reordered, but the cycles still come back
     indexed by CSR task: they correlate with the task's own features."""
     g = graphs.rmat(12, 8, seed=4)
-    cyc = costmodel.record_cycles(g, hub_threshold=-1, schedule="heuristic", tail_gap=-1).cpu().numpy().astype(np.int64)
+    cyc = costmodel.record_cycles(g, hub_threshold=-1, schedule="heuristic", tail_share=-1).cpu().numpy().astype(np.int64)
     assert cyc.size == g.nnz // 2
     assert np.all(cyc > 0)
     F = mlp.task_features(g.offsets, g.nbrs)
@@ -101,13 +101,13 @@ def test_schedules_exact(torch, schedule):
     # hub 0: the default threshold; 64: a long-task list of most tasks, many
     # of them split; -1: no hub split (the learned schedule still lists the
     # tasks above its own threshold)
-    # tail_gap -1: the last batches are always reordered; 0: only when the
+    # tail_share -1: the last batches are always reordered; 0: only when the
     # keys predict a costly batch at the end
     for hub in (0, 64, -1):
-        for gap in (-1, 0):
+        for share in (-1, 0):
             got, st, tm = triad.triad_census_device(g.n, g.nnz, *d, schedule=schedule, hub_threshold=hub, chunk=256,
-                                                    tail_gap=gap, **kw)
-            assert got == want, (hub, gap)
+                                                    tail_share=share, **kw)
+            assert got == want, (hub, share)
 
 
 def test_wave_spans(torch):
