@@ -220,6 +220,7 @@ struct EmitArgs {
   const uint32_t* ustart;
   const int64_t* tpre;
   uint64_t* tasks;
+  uint32_t* tskip;        // per task: entries of N(v) below u
   int64_t hub_threshold;  // < 0: no hub tasks
   uint64_t* long_segs;  // u << 32 | segment index within the row
   unsigned long long* long_count;
@@ -227,16 +228,30 @@ struct EmitArgs {
 };
 
 // One task per active lane: row u (entries from b, degree du), k = index of v
-// in the row, t = task index.
+// in the row, t = task index. Also records how many ids of N(v) lie below u
+// (binary search in N(v)): a whole task's merge starts N(v) at u.
 __device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int64_t u, int64_t b, int64_t du, uint32_t k,
                                           int64_t t) {
   if (!act) return;
   uint64_t tk = ((uint64_t)u << 32) | k;
-  if (e.hub_threshold >= 0) {
-    const uint32_t v = e.packed[b + k] >> 2;
-    if (du + (e.off[v + 1] - e.off[v]) > e.hub_threshold) tk |= HUB_BIT;
-  }
+  const uint32_t v = e.packed[b + k] >> 2;
+  const int64_t bv = e.off[v];
+  const uint32_t dv = (uint32_t)(e.off[v + 1] - bv);
+  if (e.hub_threshold >= 0 && du + dv > e.hub_threshold) tk |= HUB_BIT;
   e.tasks[t] = tk;
+  // ids of N(v) below u
+  const uint32_t key = (uint32_t)u << 2;
+  uint32_t lo = 0, len = dv;
+  while (len > 0) {
+    const uint32_t half = len >> 1;
+    if (e.packed[bv + lo + half] < key) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  e.tskip[t] = lo;
 }
 
 __global__ void k_emit_short(EmitArgs e) {
@@ -352,6 +367,7 @@ struct CensusArgs {
   const int64_t* off;
   const uint32_t* packed;
   const uint32_t* ustart;  // per row: entries below the row's own id
+  const uint32_t* tskip;   // per task (indexed like tasks): entries of N(v) below u
   const uint64_t* tasks;   // the task queue
   const uint64_t* htasks;  // the task words the hub list indexes
   const int64_t* order;    // optional: queue position -> index into tasks
@@ -401,10 +417,11 @@ __device__ uint32_t global_split(const uint32_t* A, uint32_t la, const uint32_t*
 
 // One batch of work items, one item per lane (lane < cnt). An item merges
 // A = packed[aoff .. aoff+la) (a range of N(u)) with B = packed[boff ..
-// boff+lb) (a range of N(v)). A starts at the first id of N(u) above u: an
-// id w < u is never counted (Fig. 5 step 2.1.4), and the intersection sizes
-// that complete the dyadic counts follow from the triangle classes
-// (k_finalize), so the ids below u are not needed.
+// boff+lb) (a range of N(v)). A starts at the first id of N(u) above u and,
+// for a whole task, B at u: an id w < u is never counted (Fig. 5 step
+// 2.1.4), and the intersection sizes that complete the dyadic counts follow
+// from the triangle classes (k_finalize), so the ids below u are not needed.
+// (Chunks of split tasks keep all of N(v).)
 // uf = u | kind << 30 with kind 0 = a later chunk of a split task, 1 = its
 // first chunk, 2 = a whole task; the first two kinds also add their task's
 // dyadic term dyad = n - d(u) - d(v) (Fig. 5 step 2.1.3). vf = v << 2 | f_uv.
@@ -507,12 +524,15 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
           const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
           const int64_t au0 = g.off[u], au1 = g.off[u + 1];
           const uint32_t pv = g.packed[au0 + (uint32_t)tk];
-          bt.boff = g.off[pv >> 2];
-          bt.lb = (uint32_t)(g.off[(pv >> 2) + 1] - bt.boff);
+          const int64_t bv0 = g.off[pv >> 2], bv1 = g.off[(pv >> 2) + 1];
+          // never past the list's end, whatever the count says
+          const uint32_t sv = min(g.tskip[bt.tid], (uint32_t)(bv1 - bv0));
+          bt.boff = bv0 + sv;
+          bt.lb = (uint32_t)(bv1 - bt.boff);
           // the ids of N(u) above u
           bt.aoff = au0 + g.ustart[u];
           bt.la = (uint32_t)(au1 - bt.aoff);
-          const uint32_t du = (uint32_t)(au1 - au0), dv = bt.lb;
+          const uint32_t du = (uint32_t)(au1 - au0), dv = bt.lb + sv;
           bt.uf = u | (2u << 30);
           bt.vf = pv;
           int64_t nn = g.n;
@@ -1130,6 +1150,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   int64_t ntasks = 0, nhub = 0;
   uint32_t errh = 0;
   uint64_t* tasks = nullptr;
+  uint32_t* tskip = nullptr;
   int64_t* order = nullptr;
   uint64_t* hub_task = nullptr;
   int64_t *hub_nch = nullptr, *hub_pre = nullptr;
@@ -1149,13 +1170,14 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   }
   if (ntasks > 0) {
     ALLOC(tasks, ntasks);
+    ALLOC(tskip, ntasks);
     const int64_t hub_cap = hub_thr >= 0 ? ntasks : 0;
     ALLOC(hub_task, hub_cap);
     ALLOC(hub_nch, hub_cap);
     ALLOC(hub_pre, hub_cap + 1);
     uint64_t* long_segs = nullptr;
     ALLOC(long_segs, emit_seg_cap(n, ntasks));
-    const EmitArgs e{n, off, packed, ustart, tpre, tasks, hub_thr, long_segs, acc + 19, err};
+    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, hub_thr, long_segs, acc + 19, err};
     launch_emit(e, s);
     // A schedule reorders the last batches of the queue: in place, or, with
     // per-task cycle recording, through a queue-position -> task index map
@@ -1163,8 +1185,8 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     if (sched) {
       if (o.task_cycles) ALLOC(order, ntasks);
       const int64_t nwaves = (int64_t)census_groups(waves, variant, o.task_cycles ? 1 : 0, o.grid_groups) * waves;
-      if (int st = schedule_tail(sched, o.model, n, off, ustart, packed, tasks, ntasks, order, o.tail_share, nwaves,
-                                 scratch, s))
+      if (int st = schedule_tail(sched, o.model, n, off, ustart, packed, tasks, tskip, ntasks, order, o.tail_share,
+                                 nwaves, scratch, s))
         return st;
     }
     if (hub_thr >= 0)
@@ -1189,6 +1211,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.off = off;
     a.packed = packed;
     a.ustart = ustart;
+    a.tskip = tskip;
     a.tasks = tasks;
     a.htasks = tasks;
     a.order = order;
@@ -1372,7 +1395,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   p->nnz = nnz;
   p->vbase = vbase;
   p->out = d_out;
-  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr;
+  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr, *tskip = nullptr;
   uint64_t* long_segs = nullptr;
   int64_t *ntask = nullptr, *tpre = nullptr, *bsum = nullptr;
   uint64_t* tasks = nullptr;
@@ -1380,7 +1403,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   const int64_t ntasks = nnz / 2;
   if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 3) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
       plan_alloc(p, &ntask, nv) || plan_alloc(p, &tpre, nv + 1) || plan_alloc(p, &bsum, nv / SCAN_B + 2) ||
-      plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks) ||
+      plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks) || plan_alloc(p, &tskip, ntasks) ||
       plan_alloc(p, &long_segs, emit_seg_cap(nv, ntasks))) {
     plan_free(p);
     (void)hipGetLastError();
@@ -1391,6 +1414,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   a.off = off;
   a.packed = packed;
   a.ustart = ustart;
+  a.tskip = tskip;
   a.tasks = tasks;
   a.htasks = tasks;
   a.order = nullptr;
@@ -1431,7 +1455,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
     scan_excl_pre(ntask, nv, tpre, bsum, s);
     k_check_tasks<<<1, 64, 0, s>>>(tpre, nv, nnz, p->err);
     if (ntasks > 0) {
-      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, -1, long_segs, q + 2, p->err};
+      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, -1, long_segs, q + 2, p->err};
       launch_emit(ea, s);
       (void)launch_census(waves, variant, a, groups, s);
     }

@@ -492,22 +492,31 @@ static int stable_bin_order(const uint8_t* bin, int64_t m, int64_t chunk, int64_
 // Queue batch from + i takes task batch border[i]: the task words moved into
 // tmp (then copied back), or the task indices written to order.
 __global__ void k_apply_batches(const int64_t* __restrict__ border, int64_t from, int64_t tail,
-                                const uint64_t* __restrict__ tasks, uint64_t* __restrict__ tmp,
+                                const uint64_t* __restrict__ tasks, const uint32_t* __restrict__ tskip,
+                                uint64_t* __restrict__ tmp, uint32_t* __restrict__ tmp_skip,
                                 int64_t* __restrict__ order, const uint32_t* __restrict__ skip) {
   if (*skip) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x, m = tail * BATCH;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
     const int64_t src = border[j / BATCH] * BATCH + (j % BATCH);
-    if (order) order[from * BATCH + j] = src;
-    else tmp[j] = tasks[src];
+    if (order) {
+      order[from * BATCH + j] = src;
+    } else {
+      tmp[j] = tasks[src];
+      tmp_skip[j] = tskip[src];
+    }
   }
 }
 
-__global__ void k_copy_back(const uint64_t* __restrict__ tmp, int64_t m, uint64_t* __restrict__ dst,
+__global__ void k_copy_back(const uint64_t* __restrict__ tmp, const uint32_t* __restrict__ tmp_skip, int64_t m,
+                            uint64_t* __restrict__ dst, uint32_t* __restrict__ dst_skip,
                             const uint32_t* __restrict__ skip) {
   if (*skip) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) dst[j] = tmp[j];
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += stride) {
+    dst[j] = tmp[j];
+    dst_skip[j] = tmp_skip[j];
+  }
 }
 
 __global__ void k_iota64(int64_t* __restrict__ p, int64_t m) {
@@ -516,8 +525,8 @@ __global__ void k_iota64(int64_t* __restrict__ p, int64_t m) {
 }
 
 int schedule_tail(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* ustart,
-                  const uint32_t* packed, uint64_t* tasks, int64_t ntasks, int64_t* order, int32_t tail_share,
-                  int64_t nwaves, Scratch& scratch, hipStream_t s) {
+                  const uint32_t* packed, uint64_t* tasks, uint32_t* tskip, int64_t ntasks, int64_t* order,
+                  int32_t tail_share, int64_t nwaves, Scratch& scratch, hipStream_t s) {
   if (mode == 2 && !model) return fail(TRIAD_EINVAL, "learned schedule without a model");
   if (order && ntasks > 0) hipLaunchKernelGGL(k_iota64, dim3(grid_of(ntasks, 256, 65536)), dim3(256), 0, s, order, ntasks);
   // full batches only: a partial last batch stays last
@@ -550,13 +559,20 @@ int schedule_tail(int mode, const float* model, int64_t n, const int64_t* off, c
                        (const uint64_t*)tasks, ntasks, from, nfull - ns, bin, (float*)nullptr, (float*)nullptr,
                        (const uint32_t*)skip);
   if (int st = stable_bin_order(bin, tail, SCHED_CHUNK, from, border, skip, scratch, s)) return st;
+  // the task words move together with their N(v) skip counts
   uint64_t* tmp = nullptr;
-  if (!order) ALLOC(tmp, tail * BATCH);
+  uint32_t* tmp_skip = nullptr;
+  if (!order) {
+    ALLOC(tmp, tail * BATCH);
+    ALLOC(tmp_skip, tail * BATCH);
+  }
   hipLaunchKernelGGL(k_apply_batches, dim3(grid_of(tail * BATCH, 256, 65536)), dim3(256), 0, s, (const int64_t*)border,
-                     from, tail, (const uint64_t*)tasks, tmp, order, (const uint32_t*)skip);
+                     from, tail, (const uint64_t*)tasks, (const uint32_t*)tskip, tmp, tmp_skip, order,
+                     (const uint32_t*)skip);
   if (!order)
     hipLaunchKernelGGL(k_copy_back, dim3(grid_of(tail * BATCH, 256, 65536)), dim3(256), 0, s, (const uint64_t*)tmp,
-                       tail * BATCH, tasks + from * BATCH, (const uint32_t*)skip);
+                       (const uint32_t*)tmp_skip, tail * BATCH, tasks + from * BATCH, tskip + from * BATCH,
+                       (const uint32_t*)skip);
   HIPCHK(hipGetLastError());
   return TRIAD_OK;
 }

@@ -102,14 +102,15 @@ constexpr int BATCH = 64;
 // mode 2: the learned model's predicted log2 cycles (model = device weights).
 constexpr int SCHED_BINS = 128;
 constexpr int64_t SCHED_TAIL_DIV = 10, SCHED_TAIL_MIN = 4096;
-// Reorders the task list in place, or, if order is not null, leaves it and
-// writes order[queue position] = task index for all ntasks positions. The
+// Reorders the task list (with tskip, each task's count of N(v) ids below u)
+// in place, or, if order is not null, leaves both and writes order[queue
+// position] = task index for all ntasks positions. The
 // reordering happens only when a batch among the last 8,192 is predicted to
 // cost more than the mean of the last 32,768 by tail_share / 10,000 (0: the
 // default 30; < 0: always) of one wavefront's share of the whole census, the
 // census running on nwaves wavefronts; ustart[u] = ids of row u below u.
 int schedule_tail(int mode, const float* model, int64_t n, const int64_t* off, const uint32_t* ustart,
-                  const uint32_t* packed, uint64_t* tasks, int64_t ntasks, int64_t* order, int32_t tail_share,
-                  int64_t nwaves, Scratch& scratch, hipStream_t s);
+                  const uint32_t* packed, uint64_t* tasks, uint32_t* tskip, int64_t ntasks, int64_t* order,
+                  int32_t tail_share, int64_t nwaves, Scratch& scratch, hipStream_t s);
 
 }  // namespace triad
