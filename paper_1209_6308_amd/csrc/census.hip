@@ -221,6 +221,7 @@ struct EmitArgs {
   const int64_t* tpre;
   uint64_t* tasks;
   uint32_t* tskip;        // per task: entries of N(v) below u
+  int32_t count_below;    // 0: write 0 to tskip (the merge then takes all of N(v))
   int64_t hub_threshold;  // < 0: no hub tasks
   uint64_t* long_segs;  // u << 32 | segment index within the row
   unsigned long long* long_count;
@@ -241,7 +242,7 @@ __device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int64_t u
   e.tasks[t] = tk;
   // ids of N(v) below u
   const uint32_t key = (uint32_t)u << 2;
-  uint32_t lo = 0, len = dv;
+  uint32_t lo = 0, len = e.count_below ? dv : 0u;
   while (len > 0) {
     const uint32_t half = len >> 1;
     if (e.packed[bv + lo + half] < key) {
@@ -1177,7 +1178,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     ALLOC(hub_pre, hub_cap + 1);
     uint64_t* long_segs = nullptr;
     ALLOC(long_segs, emit_seg_cap(n, ntasks));
-    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, hub_thr, long_segs, acc + 19, err};
+    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, 1, hub_thr, long_segs, acc + 19, err};
     launch_emit(e, s);
     // A schedule reorders the last batches of the queue: in place, or, with
     // per-task cycle recording, through a queue-position -> task index map
@@ -1455,7 +1456,9 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
     scan_excl_pre(ntask, nv, tpre, bsum, s);
     k_check_tasks<<<1, 64, 0, s>>>(tpre, nv, nnz, p->err);
     if (ntasks > 0) {
-      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, -1, long_segs, q + 2, p->err};
+      // small graphs: the search for the ids of N(v) below u would cost more
+      // than it saves
+      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, 0, -1, long_segs, q + 2, p->err};
       launch_emit(ea, s);
       (void)launch_census(waves, variant, a, groups, s);
     }
