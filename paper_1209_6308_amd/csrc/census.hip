@@ -9,12 +9,14 @@
 //               Sec. 6 / Fig. 7, built once on the device)
 //   scan        exclusive prefix of tasks(u): the collapsed (u,v) task space
 //               of Fig. 5 steps 2 and 2.1
-//   k_emit_*    task list in CSR order (short rows one lane each, long rows one
-//               wavefront each); tasks whose merge length d(u)+d(v) exceeds
-//               the hub threshold go to the hub list instead
+//   k_emit_*    task list in CSR order (short rows one lane each, long rows in
+//               segments, one wavefront each) with each task's count of N(v)
+//               ids below u; tasks whose merge length d(u)+d(v) exceeds the
+//               hub threshold go to the hub list instead
 //   k_census    persistent wavefronts: hub chunks first, then tasks; each
 //               item merges a range of N(u) with a range of N(v)
-//   k_finalize  003 = C(n,3) - sum of the rest, in two 64-bit words
+//   k_finalize  the common-neighbour part of 012 and 102 from the triangle
+//               classes; 003 = C(n,3) - sum of the rest, in two 64-bit words
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -434,8 +436,8 @@ struct Batch {
 };
 
 // Adds the batch's dyadic terms n - d(u) - d(v) (Fig. 5 step 2.1.3; the
-// intersection part is counted by the merge) to counter 012 or 102 by the u-v
-// dyad: one wave reduction and one atomic per counter when the whole batch
+// common-neighbour part is added by k_finalize) to counter 012 or 102 by the
+// u-v dyad: one wave reduction and one atomic per counter when the whole batch
 // belongs to one graph, per-lane atomics otherwise (batched census only).
 template <bool BAT>
 __device__ void add_dyads(const CensusArgs& g, int lane, const Batch& bt) {
