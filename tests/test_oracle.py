@@ -260,3 +260,42 @@ def test_partial_censuses_add_up():
 def test_wedge_matches_sweep_rmat14():
     g = graphs.rmat(14, 16, seed=4, recip_p=0.2)
     assert oracle.wedge_census(g) == oracle.census_mt(g)
+
+
+def _common_neighbour_sums(n, s, d):
+    """Sum over edges {u, v} of |N(u) ∩ N(v)|, split by the u-v dyad
+    (asymmetric, mutual), straight from the arc list."""
+    adj = [set() for _ in range(n)]
+    arcs = set()
+    for a, b in zip(s.tolist(), d.tolist()):
+        adj[a].add(b)
+        adj[b].add(a)
+        arcs.add((a, b))
+    asym = mut = 0
+    for u in range(n):
+        for v in adj[u]:
+            if v <= u:
+                continue
+            c = len(adj[u] & adj[v])
+            if (u, v) in arcs and (v, u) in arcs:
+                mut += c
+            else:
+                asym += c
+    return asym, mut
+
+
+@pytest.mark.parametrize("n,density,recip,seed", [(30, 0.3, 0.3, 1), (60, 0.15, 0.0, 2), (60, 0.2, 1.0, 3),
+                                                  (120, 0.08, 0.5, 4)])
+def test_common_neighbours_from_triangle_classes(n, density, recip, seed):
+    """Reading 12: summed over the asymmetric and over the mutual edges, the
+    common-neighbour counts of the dyadic terms follow from the triangle
+    classes (a triangle lies in the common neighbourhood of each of its three
+    edges; its class fixes how many of them are mutual). Checked against the
+    brute-force census and sets built from the arc list."""
+    s, d = random_digraph(n, density, recip, seed)
+    c = oracle.brute(n, s, d)
+    T = dict(zip(TYPES, c))
+    one_mutual = T["120D"] + T["120U"] + T["120C"]
+    asym, mut = _common_neighbour_sums(n, s, d)
+    assert asym == 3 * (T["030T"] + T["030C"]) + 2 * one_mutual + T["210"]
+    assert mut == one_mutual + 2 * T["210"] + 3 * T["300"]
