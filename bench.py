@@ -9,13 +9,24 @@ count), with the graph already resident in HBM. Prints ONE JSON line.
                     [--copy-calibration]   # plain copy kernel for counter scaling
 
 Metric: edge-pairs merged per second (an edge-pair is one task (u,v), u < v,
-over a symmetric edge), plus the census kernel's fraction of the HBM peak
-computed from algorithmic bytes B_alg = sum over tasks of 4.25*(entries merged)
-+ 32 (4-byte id and a quarter byte of direction flags per streamed entry, plus
-the two offset pairs; the merge reads the ids of N(u) above u, d+(u) of them,
-and N(v) from u on, d(v) - i entries when u is the i-th lowest neighbour of v)
-= 4.25 * (sum_x d+(x)^2 + sum_x (d(x) d-(x) - d-(x)(d-(x)-1)/2)) + 32 * m_sym,
-d-(x) = d(x) - d+(x) the neighbours below x.
+over a symmetric edge).
+
+Roofline of the census kernel: it is bound by vector-instruction issue, not by
+HBM (its DRAM traffic is about a third of the HBM peak). `roofline` therefore
+reports the vector unit: achieved = SQ_INSTS_VALU per launch (rocprofv3 counter,
+profiles/counters_k_census_<workload>.json, valid while the kernel source hash
+matches) x 64 lanes / the kernel's live duration, against the issue peak of
+256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12 32-bit lane-operations/s (a
+wave64 vector instruction occupies a 16-lane SIMD for 4 cycles).
+Beside it, `roofline.hbm` gives the algorithmic-byte figures: the metric's own
+B_full = sum over tasks of 4.25*(d(u)+d(v)) + 32 (whole lists; 4-byte id and a
+quarter byte of direction flags per entry, plus the two offset pairs), the
+bytes of the merge as the kernel runs it, B_trim = 4.25 * (sum_x d+(x)^2 +
+sum_x (d(x) d-(x) - d-(x)(d-(x)-1)/2)) + 32 * m_sym (N(u) above u, d+(u) ids,
+and N(v) from u on, d(v) - i ids when u is the i-th lowest neighbour of v;
+d-(x) = d(x) - d+(x) the neighbours below x), each over the kernel time and
+the 8 TB/s peak, and the measured DRAM bytes (FETCH_SIZE + WRITE_SIZE scaled
+by a plain copy) over the same peak.
 """
 from __future__ import annotations
 
@@ -29,6 +40,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+# vector issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (32-bit lane-ops/s, in T)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 WORKLOAD_TEXT = {
     "rmat24": "R-MAT scale 24 (16,777,216 vertices), edge factor 16, a/b/c/d = .57/.19/.19/.05, seed 1, "
@@ -43,9 +56,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, budget_entries=6.0e10, seed=7):
+def cpu_baseline(g, budget_entries=6.0e10, single_budget=4.0e9, seed=7):
     """The oracle (test infrastructure) on a bounded sample of the same
-    workload's tasks, on all host cores; rate in edge-pairs/s."""
+    workload's tasks, on all host cores, and on one core with a smaller
+    sample; rates in edge-pairs/s."""
     import numpy as np
 
     import oracle
@@ -55,18 +69,23 @@ def cpu_baseline(g, budget_entries=6.0e10, seed=7):
     del rows
     ntasks = tasks.size
     total_entries = int(np.dot(d, d))  # sum over tasks of d(u) + d(v)
-    frac = min(1.0, budget_entries / max(1, total_entries))
-    stride = max(1, int(round(1.0 / frac)))
-    off = int(np.random.default_rng(seed).integers(0, stride))
-    sample = tasks[off::stride].copy()
-    del tasks
+
+    def timed(budget, threads, salt):
+        frac = min(1.0, budget / max(1, total_entries))
+        stride = max(1, int(round(1.0 / frac)))
+        off = int(np.random.default_rng(seed + salt).integers(0, stride))
+        sample = tasks[off::stride].copy()
+        t0 = time.perf_counter()
+        oracle.census_tasks(g, sample, nthreads=threads)
+        dt = time.perf_counter() - t0
+        return sample.size / dt, (f"every {stride}th task of the {g.name} task list in CSR order (offset {off}): "
+                                  f"{sample.size} of {ntasks} tasks, {dt:.1f} s wall")
+
     threads = max(1, len(os.sched_getaffinity(0)))
-    t0 = time.perf_counter()
-    oracle.census_tasks(g, sample, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": sample.size / dt, "unit": "edge-pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th task of the {g.name} task list in CSR order (offset {off}): "
-                      f"{sample.size} of {ntasks} tasks, {dt:.1f} s wall"}
+    v, text = timed(budget_entries, threads, 0)
+    v1, text1 = timed(single_budget, 1, 1)
+    return {"value": v, "unit": "edge-pairs/s", "cores": threads, "kind": "oracle", "sample": text,
+            "single_core": {"value": v1, "unit": "edge-pairs/s", "cores": 1, "sample": text1}}
 
 
 def list_byte_sums(d_off, d_nbr, n):
@@ -106,6 +125,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-schedules", action="store_true", help="skip the heuristic / learned comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched null-model ensemble comparison")
+    ap.add_argument("--no-cl22", action="store_true", help="skip the schedule comparison on the Chung-Lu graph")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
@@ -126,45 +146,9 @@ def main():
     st = g.stats()
     log(f"generated {args.workload} in {time.time() - t0:.1f}s: {st}")
     d_off, d_nbr, d_flg = triad.to_device(g, "cuda")
-    d_out = torch.empty(17, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
     models = {}
-
-    def run(schedule, steps, warmup, spans=False):
-        kw = {"schedule": schedule}
-        if schedule == "learned":
-            if "learned" not in models:
-                from paper_1209_6308_amd import costmodel
-                t0 = time.time()
-                models["learned"] = costmodel.load_or_train(stream=stream)
-                models["report"] = costmodel.last_training_report()
-                models["report"]["train_seconds"] = round(time.time() - t0, 1)
-                log(f"cost model trained: {models['report']}")
-            kw["model"] = models["learned"]
-        for i in range(warmup):
-            triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream, d_out=d_out, **kw)
-            log(f"{schedule}: warmup {i + 1}/{warmup} done")
-        torch.cuda.synchronize()
-        census_ms, counts, tasks_ms = [], None, []
-        t0 = time.perf_counter()
-        for i in range(steps):
-            counts, status, tm = triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream,
-                                                           d_out=d_out, **kw)
-            census_ms.append(tm["census_ms"])
-            tasks_ms.append(tm["tasks_ms"])
-            log(f"{schedule}: step {i + 1}/{steps}: census kernel {tm['census_ms']:.1f} ms")
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        out = {"wall_s": wall, "census_ms": census_ms, "tasks_ms": tasks_ms, "counts": counts, "waves": tm["waves"]}
-        if spans:
-            span = torch.zeros((tm["waves"], 2), dtype=torch.int64, device="cuda")
-            triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream, d_out=d_out, wave_span=span,
-                                      **kw)
-            sp = span.cpu().numpy().astype("float64")
-            busy = sp[:, 1] - sp[:, 0]
-            out["makespan_imbalance"] = float((sp[:, 1].max() - sp[:, 0].min()) / busy.mean() - 1.0)
-            out["wave_end_spread_ms"] = float((sp[:, 1].max() - sp[:, 1].min()) / 1e5)
-        return out
+    run = make_runner(torch, triad, g, (d_off, d_nbr, d_flg), stream, models)
 
     main = run(args.schedule, args.steps, args.warmup, spans=not args.no_schedules)
     counts = main["counts"]
@@ -174,21 +158,10 @@ def main():
     kern_s = sum(main["census_ms"]) / len(main["census_ms"]) / 1e3
     # algorithmic bytes of one census: per task (u, v) the ids of N(u) above u
     # and of N(v) from u on, 4.25 B each (id + flag), plus 32 B of offsets
-    s_above2, s_d_below = list_byte_sums(d_off, d_nbr, g.n)
-    b_alg = 4.25 * (s_above2 + s_d_below) + 32.0 * st["m_sym"]
-    achieved = b_alg / kern_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_census", "kernel_ms": round(kern_s * 1e3, 2),
-            "algorithmic_bytes_per_launch": b_alg, "sum_dplus2": s_above2, "sum_d_dminus": s_d_below}
-    tfile = os.path.join(ROOT, "profiles", f"traffic_k_census_{args.workload}.json")
-    if os.path.exists(tfile):
-        with open(tfile) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_hash") == kernel_source_hash():
-            roof["traffic"] = tr["hbm_bytes_per_launch"]
+    roof = census_roofline(args.workload, kern_s, d_off, d_nbr, g.n, st)
+    b_alg = roof["hbm"]["alg_bytes_trimmed"]
     rec = {
-        "metric": "edge-pairs merged/s (R-MAT s24), census kernel % of HBM peak from algorithmic bytes",
+        "metric": "edge-pairs merged/s (R-MAT s24); census kernel roofline (vector issue; HBM figures beside it)",
         "value": round(value, 1),
         "unit": "edge-pairs/s",
         "n_gpus": 1,
@@ -207,35 +180,141 @@ def main():
         "roofline": roof,
     }
 
-    def summary(r):
-        k = sum(r["census_ms"]) / len(r["census_ms"])
-        d = {"edge_pairs_per_s": round(st["m_sym"] * len(r["census_ms"]) / r["wall_s"], 1),
-             "census_kernel_ms": round(k, 2), "schedule_ms": round(sum(r["tasks_ms"]) / len(r["tasks_ms"]), 2),
-             "hbm_frac_alg": round(b_alg / (k / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
-        if "makespan_imbalance" in r:
-            d["makespan_imbalance"] = round(r["makespan_imbalance"], 4)
-            d["wave_end_spread_ms"] = round(r["wave_end_spread_ms"], 3)
-        return d
-
     if not args.no_schedules:
-        sched = {args.schedule: summary(main)}
+        sched = {args.schedule: schedule_summary(main, st["m_sym"], b_alg)}
         for other in ("plain", "heuristic", "learned"):
             if other == args.schedule:
                 continue
             r = run(other, args.steps, 1, spans=True)
             if r["counts"] != counts:
                 raise SystemExit(f"schedule {other} changed the census")
-            sched[other] = summary(r)
+            sched[other] = schedule_summary(r, st["m_sym"], b_alg)
         sched["identical_counts"] = True
         if "report" in models:
             sched["cost_model"] = models["report"]
         rec["schedules"] = sched
+        if args.workload != "cl22" and not args.no_cl22:
+            rec["schedules_cl22"] = compare_schedules(torch, graphs, triad, "cl22", min(args.steps, 5), stream,
+                                                      models)
     if not args.no_batched:
         rec["batched"] = batched_bench(torch)
     if not args.no_cpu_baseline:
         log("timing the oracle on a task sample (host cores)")
         rec["cpu_baseline"] = cpu_baseline(g)
     print(json.dumps(rec), flush=True)
+
+
+def make_runner(torch, triad, g, dev, stream, models):
+    """run(schedule, steps, warmup, spans) -> timings and counts of repeated
+    census calls on the device-resident graph `dev` = (offsets, ids, flags)."""
+    d_off, d_nbr, d_flg = dev
+    d_out = torch.empty(17, dtype=torch.int64, device="cuda")
+
+    def run(schedule, steps, warmup, spans=False):
+        kw = {"schedule": schedule}
+        if schedule == "learned":
+            if "learned" not in models:
+                from paper_1209_6308_amd import costmodel
+                t0 = time.time()
+                models["learned"] = costmodel.load_or_train(stream=stream)
+                models["report"] = costmodel.last_training_report()
+                models["report"]["train_seconds"] = round(time.time() - t0, 1)
+                log(f"cost model trained: {models['report']}")
+            kw["model"] = models["learned"]
+        for i in range(warmup):
+            triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream, d_out=d_out, **kw)
+            log(f"{g.name} {schedule}: warmup {i + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        census_ms, counts, tasks_ms = [], None, []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            counts, status, tm = triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream,
+                                                           d_out=d_out, **kw)
+            census_ms.append(tm["census_ms"])
+            tasks_ms.append(tm["tasks_ms"])
+            log(f"{g.name} {schedule}: step {i + 1}/{steps}: census kernel {tm['census_ms']:.1f} ms")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out = {"wall_s": wall, "census_ms": census_ms, "tasks_ms": tasks_ms, "counts": counts, "waves": tm["waves"]}
+        if spans:
+            span = torch.zeros((tm["waves"], 2), dtype=torch.int64, device="cuda")
+            triad.triad_census_device(g.n, g.nnz, d_off, d_nbr, d_flg, stream=stream, d_out=d_out, wave_span=span,
+                                      **kw)
+            sp = span.cpu().numpy().astype("float64")
+            busy = sp[:, 1] - sp[:, 0]
+            out["makespan_imbalance"] = float((sp[:, 1].max() - sp[:, 0].min()) / busy.mean() - 1.0)
+            out["wave_end_spread_ms"] = float((sp[:, 1].max() - sp[:, 1].min()) / 1e5)
+        return out
+
+    return run
+
+
+def schedule_summary(r, m_sym, b_alg):
+    k = sum(r["census_ms"]) / len(r["census_ms"])
+    d = {"edge_pairs_per_s": round(m_sym * len(r["census_ms"]) / r["wall_s"], 1),
+         "census_kernel_ms": round(k, 2), "schedule_ms": round(sum(r["tasks_ms"]) / len(r["tasks_ms"]), 2),
+         "hbm_frac_alg_trimmed": round(b_alg / (k / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if "makespan_imbalance" in r:
+        d["makespan_imbalance"] = round(r["makespan_imbalance"], 4)
+        d["wave_end_spread_ms"] = round(r["wave_end_spread_ms"], 3)
+    return d
+
+
+def compare_schedules(torch, graphs, triad, name, steps, stream, models):
+    """Plain / heuristic / learned census of another workload (identical counts
+    required): the learned-schedule comparison on the Chung-Lu graph."""
+    t0 = time.time()
+    g = graphs.workload(name)
+    st = g.stats()
+    log(f"generated {name} in {time.time() - t0:.1f}s: {st}")
+    dev = triad.to_device(g, "cuda")
+    run = make_runner(torch, triad, g, dev, stream, models)
+    s_above2, s_d_below = list_byte_sums(dev[0], dev[1], g.n)
+    b_alg = 4.25 * (s_above2 + s_d_below) + 32.0 * st["m_sym"]
+    out, counts = {"workload": WORKLOAD_TEXT[name], "m_sym": st["m_sym"], "steps": steps}, None
+    for sched in ("plain", "heuristic", "learned"):
+        r = run(sched, steps, 1, spans=True)
+        if counts is not None and r["counts"] != counts:
+            raise SystemExit(f"schedule {sched} changed the {name} census")
+        counts = r["counts"]
+        out[sched] = schedule_summary(r, st["m_sym"], b_alg)
+    out["identical_counts"] = True
+    out["census"] = [str(x) for x in counts]
+    return out
+
+
+def census_roofline(workload, kern_s, d_off, d_nbr, n, st):
+    """Roofline record of the census kernel (see the module docstring)."""
+    s_above2, s_d_below = list_byte_sums(d_off, d_nbr, n)
+    b_trim = 4.25 * (s_above2 + s_d_below) + 32.0 * st["m_sym"]
+    b_full = 4.25 * st["sum_d2"] + 32.0 * st["m_sym"]
+    hbm = {"peak_gbs": HBM_PEAK_GBS,
+           "alg_bytes_full": b_full, "frac_alg_full": round(b_full / kern_s / 1e9 / HBM_PEAK_GBS, 4),
+           "alg_bytes_trimmed": b_trim, "frac_alg_trimmed": round(b_trim / kern_s / 1e9 / HBM_PEAK_GBS, 4),
+           "sum_dplus2": s_above2, "sum_d_dminus": s_d_below, "dram_bytes": None, "frac_dram": None}
+    roof = {"bound": "alu", "achieved": None, "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s", "frac": None,
+            "traffic": None, "kernel": "k_census", "kernel_ms": round(kern_s * 1e3, 2),
+            "peak_basis": "vector issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, 32-bit lane-ops",
+            "counters": None, "hbm": hbm}
+    cfile = os.path.join(ROOT, "profiles", f"counters_k_census_{workload}.json")
+    if os.path.exists(cfile):
+        with open(cfile) as f:
+            c = json.load(f)
+        roof["counters"] = os.path.relpath(cfile, ROOT)
+        if c.get("kernel_source_hash") == kernel_source_hash():
+            valu = float(c["SQ_INSTS_VALU"])
+            ach = valu * 64 / kern_s / 1e12
+            roof["achieved"] = round(ach, 3)
+            roof["frac"] = round(ach / VALU_PEAK_TOPS, 4)
+            roof["valu_insts_per_launch"] = valu
+            roof["salu_insts_per_launch"] = float(c["SQ_INSTS_SALU"])
+            roof["lds_insts_per_launch"] = float(c["SQ_INSTS_LDS"])
+            roof["traffic"] = c["hbm_bytes_per_launch"]
+            hbm["dram_bytes"] = c["hbm_bytes_per_launch"]
+            hbm["frac_dram"] = round(c["hbm_bytes_per_launch"] / kern_s / 1e9 / HBM_PEAK_GBS, 4)
+        else:
+            roof["note"] = "kernel source changed since the counters were taken"
+    return roof
 
 
 def batched_bench(torch, reps=3):
@@ -292,9 +371,10 @@ def batched_bench(torch, reps=3):
 
 
 def kernel_source_hash():
+    """Hash of the sources the census kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for fn in sorted(os.listdir(os.path.join(ROOT, "paper_1209_6308_amd", "csrc"))):
+    for fn in ("census.hip", "triad_internal.h"):
         with open(os.path.join(ROOT, "paper_1209_6308_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

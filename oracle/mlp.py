@@ -76,6 +76,39 @@ def loss_grad(w, X, t):
     return loss, pack({"W1": gW1, "b1": gb1, "W2": gW2, "b2": gb2, "W3": gW3, "b3": gb3})
 
 
+def grad_magnitude(w, X, t):
+    """Per parameter, a bound on the size of every quantity that enters its
+    gradient: loss_grad's chain rule with each factor replaced by its magnitude,
+    the forward values by the sums of the magnitudes of their terms, and the
+    residual y - t by |y - t| + |y|'s term magnitudes + |t| (the residual of a
+    rounded y is off by a fraction of those, not of |y - t|). A float32
+    evaluation sums the same products in some order, so its rounding error is
+    at most (depth * 2^-24) times this, depth being the longest chain of
+    roundings (the dot products of the forward and backward passes, the sum
+    over samples, the activations)."""
+    P = unpack(w)
+    X = np.asarray(X, dtype=np.float64).reshape(-1, NI)
+    t = np.asarray(t, dtype=np.float64).ravel()
+    m = X.shape[0]
+    a1 = X @ P["W1"].T + P["b1"]
+    a2 = np.maximum(a1, 0.0) @ P["W2"].T + P["b2"]
+    y = np.maximum(a2, 0.0) @ P["W3"] + P["b3"]
+    aX, aW1, aW2, aW3 = np.abs(X), np.abs(P["W1"]), np.abs(P["W2"]), np.abs(P["W3"])
+    h1m = (aX @ aW1.T + np.abs(P["b1"])) * (a1 > 0)
+    h2m = (h1m @ aW2.T + np.abs(P["b2"])) * (a2 > 0)
+    ym = h2m @ aW3 + abs(P["b3"])
+    dy = 2.0 * (np.abs(y - t) + ym + np.abs(t)) / m
+    gW3 = h2m.T @ dy
+    gb3 = dy.sum()
+    dh2 = np.outer(dy, aW3) * (a2 > 0)
+    gW2 = dh2.T @ h1m
+    gb2 = dh2.sum(axis=0)
+    dh1 = (dh2 @ aW2) * (a1 > 0)
+    gW1 = dh1.T @ aX
+    gb1 = dh1.sum(axis=0)
+    return pack({"W1": gW1, "b1": gb1, "W2": gW2, "b2": gb2, "W3": gW3, "b3": gb3})
+
+
 def adam_step(w, m1, m2, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     m1 = b1 * m1 + (1 - b1) * g
     m2 = b2 * m2 + (1 - b2) * g * g

@@ -1335,6 +1335,35 @@ __global__ void k_finalize_batch(int32_t G, const int64_t* __restrict__ vbase, u
   gout[16 * (uint64_t)g] = c3 - s;
 }
 
+// Content signature of a batch for the autotuner's cache: a sum of hashes of
+// (row, offset) pairs and of the graph bases, and the sum of squared degrees.
+__device__ __forceinline__ uint64_t sig_mix(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xbf58476d1ce4e5b9ull;
+  z ^= z >> 27;
+  z *= 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+__global__ void k_batch_signature(int32_t G, int64_t nv, const int64_t* __restrict__ vbase,
+                                  const int64_t* __restrict__ off, unsigned long long* __restrict__ sig) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint64_t h = 0, s2 = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= nv; i += stride) {
+    h += sig_mix((uint64_t)off[i] * 0x9e3779b97f4a7c15ull + (uint64_t)i);
+    if (i < nv) {
+      const uint64_t d = (uint64_t)(off[i + 1] - off[i]);
+      s2 += d * d;
+    }
+    if (i <= G) h += sig_mix(~((uint64_t)vbase[i] * 0xd1b54a32d192ed03ull + (uint64_t)i));
+  }
+  h = wave_sum64(h);
+  s2 = wave_sum64(s2);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&sig[0], (unsigned long long)h);
+    atomicAdd(&sig[1], (unsigned long long)s2);
+  }
+}
+
 // Three-pass exclusive scan with caller-provided block sums (capturable).
 static void scan_excl_pre(const int64_t* in, int64_t m, int64_t* out, int64_t* bsum, hipStream_t s) {
   const int64_t nb = (m + SCAN_B - 1) / SCAN_B;
@@ -1379,6 +1408,21 @@ static hipError_t plan_alloc(triad_batch_plan* p, T** ptr, int64_t count) {
   return e;
 }
 
+// Graph bases of a batch: vbase[0] = 0, non-decreasing, vbase[G] = nv, and
+// every member below BATCH_MAX_N vertices (C(n_g, 3) < 2^64).
+constexpr int64_t BATCH_MAX_N = 4801281;
+static int check_vbase(int32_t G, int64_t nv, const int64_t* hv) {
+  if (hv[0] != 0) return fail(TRIAD_EINVAL, "vbase[0] must be 0");
+  if (hv[G] != nv) return fail(TRIAD_EINVAL, "vbase[G] must equal the number of rows nv");
+  for (int32_t g = 0; g < G; ++g) {
+    if (hv[g + 1] < hv[g]) return fail(TRIAD_EINVAL, "vbase is not non-decreasing at graph " + std::to_string(g));
+    if (hv[g + 1] - hv[g] >= BATCH_MAX_N)
+      return fail(TRIAD_EINVAL, "graph " + std::to_string(g) + " has 4,801,281 or more vertices (its 003 count "
+                                "would not fit in 64 bits); census it on its own");
+  }
+  return TRIAD_OK;
+}
+
 static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, const int64_t* off, const int32_t* nbr,
                       const uint8_t* flg, uint64_t* d_out, const triad_opts* opts, hipStream_t s,
                       triad_batch_plan** out_plan) {
@@ -1392,6 +1436,15 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   if (waves != 1 && waves != 2 && waves != 4) return fail(TRIAD_EINVAL, "waves_per_group must be 1, 2 or 4");
   DeviceInfo di;
   if (int st = device_info(&di)) return st;
+  // The graph bases are checked on the host before anything is captured or
+  // launched: every kernel indexes rows through them, and each member's null
+  // count C(n_g, 3) is formed in 64 bits.
+  {
+    std::vector<int64_t> hv((size_t)G + 1);
+    HIPCHK(hipMemcpyAsync(hv.data(), vbase, sizeof(int64_t) * ((size_t)G + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (int st = check_vbase(G, nv, hv.data())) return st;
+  }
   triad_batch_plan* p = new triad_batch_plan;
   p->G = G;
   p->nv = nv;
@@ -1439,7 +1492,6 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   // capture the whole batched census as one graph (fills instead of memsets)
   // on a private stream: the caller's stream may be the legacy null stream,
   // which cannot be captured; launches replay it on the caller's stream
-  (void)s;
   hipStream_t cs = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1584,16 +1636,48 @@ int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t* d_vb
                          const int32_t* d_nbrs, const uint8_t* d_flags, void* hip_stream, const char* cache_path,
                          triad_opts* best) {
   if (!best) return fail(TRIAD_EINVAL, "best is NULL");
+  if (G < 1 || nv < 0 || nv >= ((int64_t)1 << 30) || nnz < 0 || !d_vbase || !d_offsets)
+    return fail(TRIAD_EINVAL, "bad batch sizes or NULL pointer");
   DeviceInfo di;
   if (int st = device_info(&di)) return st;
-  char sig[160];
-  snprintf(sig, sizeof sig, "%s|G=%d|nv=%lld|nnz=%lld", di.name.c_str(), (int)G, (long long)nv, (long long)nnz);
+  hipStream_t s = (hipStream_t)hip_stream;
+  {
+    std::vector<int64_t> hv((size_t)G + 1);
+    HIPCHK(hipMemcpyAsync(hv.data(), d_vbase, sizeof(int64_t) * ((size_t)G + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (int st = check_vbase(G, nv, hv.data())) return st;
+  }
+  // the batch's content signature: equal sizes alone do not make equal batches
+  unsigned long long hsig[2] = {0, 0};
+  {
+    unsigned long long* dsig = nullptr;
+    HIPCHK(hipMallocAsync((void**)&dsig, 2 * sizeof(unsigned long long), s));
+    k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)dsig, 2, 0);
+    k_batch_signature<<<grid_for(nv + 1, 256, 4096), 256, 0, s>>>(G, nv, d_vbase, d_offsets, dsig);
+    hipError_t e = hipMemcpyAsync(hsig, dsig, sizeof hsig, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipFreeAsync(dsig, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(TRIAD_EDEVICE, std::string("batch signature: ") + hipGetErrorString(e));
+  }
+  char sig[256];
+  snprintf(sig, sizeof sig, "%s|G=%d|nv=%lld|nnz=%lld|h=%016llx|d2=%llu", di.name.c_str(), (int)G, (long long)nv,
+           (long long)nnz, hsig[0], hsig[1]);
+  // the candidate launch shapes; a cached line naming any other is ignored
+  const int variants[4] = {V_W448_HH7 + 1, V_W512_HH6 + 1, V_W512 + 1, V_W512_HH + 1};
+  const int wavess[2] = {1, 2};
+  auto candidate = [&](int kv, int wv, int gg) {
+    for (int vi = 0; vi < 4; ++vi)
+      for (int wi = 0; wi < 2; ++wi)
+        for (int gm = 1; gm <= 2; ++gm)
+          if (kv == variants[vi] && wv == wavess[wi] && gg == census_groups(wv, kv - 1, 2, 0) * gm) return true;
+    return false;
+  };
   // cache: one JSON object per line: {"sig": "...", "kernel_variant": k, "waves_per_group": w, "grid_groups": g, "ms": t}
   if (cache_path) {
     if (FILE* f = fopen(cache_path, "r")) {
       char line[512];
       while (fgets(line, sizeof line, f)) {
-        char want[200];
+        char want[300];
         snprintf(want, sizeof want, "\"sig\": \"%s\"", sig);
         if (!strstr(line, want)) continue;
         int kv = 0, wv = 0, gg = 0;
@@ -1601,7 +1685,7 @@ int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t* d_vb
         const char* p2 = strstr(line, "\"waves_per_group\": ");
         const char* p3 = strstr(line, "\"grid_groups\": ");
         if (p1 && p2 && p3 && sscanf(p1 + 18, "%d", &kv) == 1 && sscanf(p2 + 19, "%d", &wv) == 1 &&
-            sscanf(p3 + 15, "%d", &gg) == 1) {
+            sscanf(p3 + 15, "%d", &gg) == 1 && candidate(kv, wv, gg)) {
           *best = triad_opts{};
           best->kernel_variant = kv;
           best->waves_per_group = wv;
@@ -1613,7 +1697,6 @@ int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t* d_vb
       fclose(f);
     }
   }
-  hipStream_t s = (hipStream_t)hip_stream;
   uint64_t* out = nullptr;
   HIPCHK(hipMalloc(&out, sizeof(uint64_t) * 16 * (size_t)G));
   hipEvent_t e0, e1;
@@ -1621,8 +1704,6 @@ int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t* d_vb
   HIPCHK(hipEventCreate(&e1));
   float best_ms = 1e30f;
   triad_opts bo{};
-  const int variants[4] = {V_W448_HH7 + 1, V_W512_HH6 + 1, V_W512 + 1, V_W512_HH + 1};
-  const int wavess[2] = {1, 2};
   int status = TRIAD_OK;
   for (int vi = 0; vi < 4 && status == TRIAD_OK; ++vi)
     for (int wi = 0; wi < 2 && status == TRIAD_OK; ++wi)

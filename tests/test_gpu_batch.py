@@ -92,6 +92,44 @@ def test_batch_validation_error(torch):
     assert e.value.status == triad.ERANGE
 
 
+@pytest.mark.parametrize("case", ["first", "last", "order", "too_large"])
+def test_batch_rejects_bad_bases(torch, case):
+    """Graph bases are checked on the host before any launch: a bad vbase is
+    TRIAD_EINVAL and nothing is written."""
+    B = graphs.null_ensemble(G=4, seed=7, nmin=64, nmax=100, dmin=4, dmax=8)
+    vb = B.vbase.copy()
+    nv, nnz = int(vb[-1]), B.nnz
+    if case == "first":
+        vb[0] = 1
+    elif case == "last":
+        vb[-1] = nv - 1
+    elif case == "order":
+        vb[2] = vb[1] - 1
+    else:
+        # one member of 4,801,281 vertices and no arcs: its C(n,3) exceeds 2^64
+        vb = np.array([0, 4801281], np.int64)
+        nv, nnz = 4801281, 0
+    d = [torch.from_numpy(vb).cuda()] + list(triad.batch_to_device(B))[1:]
+    if case == "too_large":
+        d[1] = torch.zeros(nv + 1, dtype=torch.int64, device="cuda")
+    G = vb.size - 1
+    out = torch.full((G, 16), 7, dtype=torch.int64, device="cuda")
+    for call in ("plan", "tune"):
+        with pytest.raises(triad.TriadError) as e:
+            if call == "plan":
+                triad.BatchPlan(G, nv, nnz, *d, d_out=out)
+            else:
+                triad.batch_autotune(G, nv, nnz, *d)
+        assert e.value.status == triad.EINVAL, (call, str(e.value))
+    assert torch.all(out == 7), "output written on error"
+    # a member of 4,801,280 vertices is accepted
+    if case == "too_large":
+        vb = np.array([0, 4801280], np.int64)
+        d = [torch.from_numpy(vb).cuda(), torch.zeros(4801281, dtype=torch.int64, device="cuda"), d[2], d[3]]
+        got = triad.triad_census_batch(1, 4801280, 0, *d)
+        assert got[0] == oracle.census(graphs.build_csr(4801280, np.zeros(0, np.int32), np.zeros(0, np.int32)))
+
+
 def test_autotune_and_cache(torch, tmp_path):
     B = graphs.null_ensemble(G=64, seed=8, nmin=64, nmax=900, dmin=4, dmax=24)
     want = [oracle.census(B.graph(g)) for g in range(B.G)]
@@ -102,6 +140,26 @@ def test_autotune_and_cache(torch, tmp_path):
     again = triad.batch_autotune(B.G, int(B.vbase[-1]), B.nnz, *d, cache_path=cache)
     assert again == best
     assert len(open(cache).read().strip().splitlines()) == 1
+    # another batch of the same sizes (member 0's ids reversed, so its degree
+    # sequence moves) has another signature: it is tuned again and appended
+    m0 = B.graph(0)
+    s0, t0 = m0.arcs()
+    r0 = graphs.build_csr(m0.n, m0.n - 1 - s0, m0.n - 1 - t0)
+    B2 = concat([r0] + [B.graph(g) for g in range(1, B.G)])
+    assert (B2.G, int(B2.vbase[-1]), B2.nnz) == (B.G, int(B.vbase[-1]), B.nnz)
+    assert not np.array_equal(B2.offsets, B.offsets)
+    d2 = triad.batch_to_device(B2)
+    triad.batch_autotune(B2.G, int(B2.vbase[-1]), B2.nnz, *d2, cache_path=cache)
+    assert len(open(cache).read().strip().splitlines()) == 2
+    # a cached line whose launch shape is not a candidate is ignored (tuned again)
+    lines = open(cache).read().strip().splitlines()
+    bad = json.loads(lines[0])
+    bad["waves_per_group"] = 3
+    with open(cache, "w") as f:
+        f.write(json.dumps(bad) + "\n")
+    third = triad.batch_autotune(B.G, int(B.vbase[-1]), B.nnz, *d, cache_path=cache)
+    assert third["waves_per_group"] in (1, 2)
+    assert len(open(cache).read().strip().splitlines()) == 2
     assert triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d, **best) == want
 
 

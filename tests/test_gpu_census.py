@@ -144,6 +144,30 @@ def test_host_pointer_entry(torch_cuda):
     assert triad.triad_census(g.n, g.offsets, g.nbrs, g.flags) == oracle.census(g)
 
 
+def test_five_argument_entry(torch_cuda):
+    """triad_census(n, csr_offsets, csr_nbrs, dir_flags, out_u64[16]) called
+    directly through the C ABI (Fig. 5's input and output: the graph in, the 16
+    counts out)."""
+    import ctypes
+    L = triad.lib()
+    for g in (graphs.workload("rmat10"), graphs.rmat(12, 8, seed=9, recip_p=0.2)):
+        out = np.zeros(16, dtype=np.uint64)
+        st = L.triad_census(g.n, g.offsets.ctypes.data, g.nbrs.ctypes.data, g.flags.ctypes.data,
+                            out.ctypes.data_as(ctypes.c_void_p))
+        assert st == triad.OK
+        assert [int(x) for x in out] == oracle.census(g)
+    # 003 above 2^64: the status says so and out[0] holds 003 mod 2^64
+    n = 4801285
+    g = graphs.from_arcs(n, [(0, 1), (1, 0), (2, 3), (n - 1, 5)])
+    out = np.zeros(16, dtype=np.uint64)
+    st = L.triad_census(g.n, g.offsets.ctypes.data, g.nbrs.ctypes.data, g.flags.ctypes.data,
+                        out.ctypes.data_as(ctypes.c_void_p))
+    want = oracle.census(g)
+    assert want[0] >= 1 << 64
+    assert st == triad.OK_003_WRAPPED
+    assert [int(x) for x in out] == [want[0] & ((1 << 64) - 1)] + want[1:]
+
+
 def _bad(kind):
     g = graphs.rmat(8, 4, seed=1)
     off, nb, fl = g.offsets.copy(), g.nbrs.copy(), g.flags.copy()

@@ -62,3 +62,18 @@ def test_task_features_by_hand():
     # tasks in CSR order: (0,1), (0,2), (0,3), (1,2)
     raw = np.array([[3, 2, 5, 2, 3, 2], [3, 2, 5, 2, 3, 1], [3, 1, 4, 1, 3, 0], [2, 2, 4, 2, 2, 0]], float)
     assert np.allclose(F, np.log2(1 + raw))
+
+
+def test_gradient_magnitude_bounds_the_gradient():
+    """The rounding bound's magnitudes dominate the gradient element by element
+    and are positive wherever a parameter takes part."""
+    rng = np.random.default_rng(4)
+    w = rand_w(5)
+    X = rng.normal(1.0, 2.0, size=(64, mlp.NI))
+    t = rng.normal(size=64)
+    _, g = mlp.loss_grad(w, X, t)
+    s = mlp.grad_magnitude(w, X, t)
+    assert s.shape == g.shape
+    assert np.all(s >= np.abs(g) * (1 - 1e-12))
+    assert s[-1] > 0  # b3 takes part in every sample
+
