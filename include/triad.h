@@ -177,6 +177,25 @@ int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t *d_vb
                          const int32_t *d_nbrs, const uint8_t *d_flags, void *hip_stream,
                          const char *cache_path, triad_opts *best);
 
+/* ------------------------------------------------------ CSR construction
+ * The compact CSR with direction bits (Sec. 6, Fig. 7) built on the device
+ * from an arc list: d_src[i] -> d_dst[i], i < narcs (DEVICE int32 arrays,
+ * endpoints in [0, n)). Self-loops are dropped and duplicate arcs merged; row x
+ * lists, ascending, every y with an arc x->y or y->x, with flag bit0 = x->y
+ * and bit1 = y->x (the single-graph input contract above). Outputs, DEVICE
+ * memory allocated by the caller: d_offsets int64[n+1], d_nbrs int32 with room
+ * for 2*narcs entries, d_flags uint8 with room for ceil(2*narcs/4) bytes (the
+ * first nnz entries and ceil(nnz/4) bytes are written); *nnz_out (host)
+ * receives nnz. device_ms (host, may be NULL) receives the device time of the
+ * construction measured with HIP events on the stream. Limits: n < 2^30,
+ * narcs < 2^31. Errors: TRIAD_EINVAL (sizes, NULL pointers), TRIAD_ERANGE (an
+ * endpoint outside [0, n); no output is written), TRIAD_ENOMEM. Scratch comes
+ * from the stream-ordered allocator, about 35 bytes per arc. The call waits
+ * for its work on hip_stream before returning. */
+int triad_csr_from_arcs(int64_t n, int64_t narcs, const int32_t *d_src, const int32_t *d_dst, void *hip_stream,
+                        int64_t *d_offsets, int32_t *d_nbrs, uint8_t *d_flags, int64_t *nnz_out,
+                        float *device_ms);
+
 /* ------------------------------------------------------- learned schedule
  * Cost model: an FP32 multilayer perceptron 6 -> 32 -> 32 -> 1 with ReLU
  * hidden layers. Parameters, packed in this order: W1[32][6], b1[32],

@@ -36,7 +36,7 @@ EXPORTS = [
     "triad_census", "triad_census_ex", "triad_census_device", "triad_validate_host",
     "triad_batch_plan_create", "triad_batch_plan_launch", "triad_batch_plan_status",
     "triad_batch_plan_destroy", "triad_census_batch", "triad_batch_autotune",
-    "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
+    "triad_csr_from_arcs", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
     "triad_mlp_train", "triad_last_error", "triad_version",
 ]
 
@@ -88,6 +88,8 @@ def lib():
             "triad_batch_plan_destroy": [vp],
             "triad_census_batch": [i32, i64, i64, vp, vp, vp, vp, po, vp, vp],
             "triad_batch_autotune": [i32, i64, i64, vp, vp, vp, vp, vp, ctypes.c_char_p, po],
+            "triad_csr_from_arcs": [i64, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64),
+                                    ctypes.POINTER(ctypes.c_float)],
             "triad_task_features": [i64, i64, vp, vp, vp, vp, ctypes.POINTER(i64)],
             "triad_mlp_forward": [vp, vp, i64, vp, vp],
             "triad_mlp_loss_grad": [vp, vp, vp, i64, vp, vp, vp],
@@ -198,6 +200,27 @@ def to_device(g, device="cuda"):
     import torch
     return (torch.from_numpy(g.offsets).to(device), torch.from_numpy(g.nbrs).to(device),
             torch.from_numpy(g.flags).to(device))
+
+
+def csr_from_arcs(n, d_src, d_dst, stream=None, timed=False):
+    """Symmetric CSR with direction flags built on the device from int32 arc
+    tensors; returns (offsets, ids, flags) device tensors trimmed to nnz (and the
+    device milliseconds if timed)."""
+    import torch
+    narcs = int(d_src.numel())
+    if int(d_dst.numel()) != narcs:
+        raise ValueError("src and dst differ in length")
+    dev = d_src.device if narcs else torch.device("cuda")
+    off = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nbr = torch.empty(max(2 * narcs, 1), dtype=torch.int32, device=dev)
+    flg = torch.empty(max((2 * narcs + 3) // 4, 1), dtype=torch.uint8, device=dev)
+    nnz = ctypes.c_int64(0)
+    ms = ctypes.c_float(0.0)
+    _check(lib().triad_csr_from_arcs(n, narcs, _tp(d_src), _tp(d_dst), _stream(stream), _tp(off), _tp(nbr),
+                                     _tp(flg), ctypes.byref(nnz), ctypes.byref(ms) if timed else None))
+    k = int(nnz.value)
+    out = (off, nbr[:k], flg[:(k + 3) // 4])
+    return out + (float(ms.value),) if timed else out
 
 
 # ------------------------------------------------------------------ batches
