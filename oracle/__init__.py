@@ -18,6 +18,9 @@ Functions (all plain C in ``liboracle.so``, wrapped with ctypes):
 * :func:`lut`           the 64-state -> 16-class table of the sweep.
 * :func:`exhaustive`    every labelled digraph on n <= 5 vertices, sweep and
                         decomposition against the brute force.
+* :func:`labelled_census` the 64-state census (states of triples a < b < c by
+                        id order, Sec. 3), by the same sweep.
+* :func:`brute64`       the 64-state census by its definition, every triple.
 """
 from __future__ import annotations
 
@@ -28,7 +31,7 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["census_oracle.c", "brute.c", "wedge.c", "selftest.c"]
+SOURCES = ["census_oracle.c", "brute.c", "wedge.c", "selftest.c", "labelled.c"]
 TYPES = ["003", "012", "102", "021D", "021U", "021C", "111D", "111U",
          "030T", "030C", "201", "120D", "120U", "120C", "210", "300"]
 
@@ -81,6 +84,10 @@ def lib():
         L.oracle_choose3.restype = None
         L.oracle_exhaustive.argtypes = [i32, vp]
         L.oracle_exhaustive.restype = i64
+        L.oracle_labelled_census.argtypes = [i64, vp, vp, vp, vp, vp]
+        L.oracle_labelled_census.restype = i32
+        L.oracle_brute64.argtypes = [i64, i64, vp, vp, vp, vp]
+        L.oracle_brute64.restype = i32
         _LIB = L
     return _LIB
 
@@ -173,3 +180,24 @@ def exhaustive(n):
     m = np.zeros(2, dtype=np.int64)
     total = lib().oracle_exhaustive(n, _p(m))
     return int(total), int(m[0]), int(m[1])
+
+
+def labelled_census(g):
+    """64 counts: state f_ab | f_ac << 2 | f_bc << 4 of the triples a < b < c
+    (state 0 with its high word)."""
+    off, nb, fl = _csr_args(g)
+    out = np.zeros(64, dtype=np.uint64)
+    hi = np.zeros(1, dtype=np.uint64)
+    lib().oracle_labelled_census(g.n, _p(off), _p(nb), _p(fl), _p(out), _p(hi))
+    return _result(out, hi)
+
+
+def brute64(n, src, dst):
+    s = np.ascontiguousarray(src, dtype=np.int32)
+    d = np.ascontiguousarray(dst, dtype=np.int32)
+    out = np.zeros(64, dtype=np.uint64)
+    hi = np.zeros(1, dtype=np.uint64)
+    if lib().oracle_brute64(n, s.size, _p(s), _p(d), _p(out), _p(hi)) < 0:
+        raise MemoryError("brute force adjacency allocation failed")
+    return _result(out, hi)
+

@@ -103,3 +103,40 @@ int oracle_brute(int64_t n, int64_t narcs, const int32_t *src, const int32_t *ds
   if (hi003) *hi003 = (uint64_t)(c003 >> 64);
   return (c003 >> 64) != 0;
 }
+
+/* The 64-state labelled census by its definition: for every triple a < b < c
+ * of vertex ids, the state f_ab | f_ac << 2 | f_bc << 4 of its three pairs
+ * (f_xy: bit0 = arc x->y, bit1 = arc y->x, 0 = no arc), counted per state.
+ * Sec. 3 of the paper: the 64 states of a labelled triad before they are
+ * condensed into 16 isomorphism classes. out[0] (no arc) is returned mod 2^64
+ * with its high word in *hi0. */
+int oracle_brute64(int64_t n, int64_t narcs, const int32_t *src, const int32_t *dst, uint64_t out[64],
+                   uint64_t *hi0) {
+  memset(out, 0, 64 * sizeof(uint64_t));
+  if (hi0) *hi0 = 0;
+  if (n < 3) return 0;
+  uint8_t *st = (uint8_t *)calloc((size_t)n * (size_t)n, 1);
+  if (!st) return -1;
+  for (int64_t i = 0; i < narcs; ++i) {
+    int64_t a = src[i], b = dst[i];
+    if (a == b) continue;
+    st[a * n + b] |= 1;
+    st[b * n + a] |= 2;
+  }
+  u128 c0 = 0;
+  for (int64_t a = 0; a < n; ++a) {
+    const uint8_t *ra = st + a * n;
+    for (int64_t b = a + 1; b < n; ++b) {
+      const uint8_t *rb = st + b * n;
+      int sab = ra[b];
+      for (int64_t c = b + 1; c < n; ++c) {
+        int s = sab | ra[c] << 2 | rb[c] << 4;
+        if (s == 0) ++c0; else out[s]++;
+      }
+    }
+  }
+  free(st);
+  out[0] = (uint64_t)c0;
+  if (hi0) *hi0 = (uint64_t)(c0 >> 64);
+  return (c0 >> 64) != 0;
+}
