@@ -139,6 +139,25 @@ int triad_census_device(int64_t n, int64_t nnz, const int64_t *csr_offsets, cons
                         const uint8_t *dir_flags, const triad_opts *opts, void *hip_stream, uint64_t *d_out,
                         uint64_t *h_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the census of
+ * triad_census_device, same arguments and results, with no allocation at all.
+ * Its scratch is one static device array of TRIAD_NOALLOC_SCRATCH_BYTES per
+ * GPU, held until the process ends; the call takes that GPU's copy (the
+ * current device's). Options: plain schedule only, task_cycles and timing
+ * NULL (else TRIAD_EINVAL). A graph whose scratch would not fit (per vertex
+ * 28 B, per CSR entry about 22 B, each buffer rounded up to 256 B; for example
+ * 2^20 vertices with 1.5 M entries fit) is rejected with TRIAD_EINVAL before
+ * anything is launched. Every call on one GPU shares its array and leaves its
+ * contents behind (each call clears what it needs): calls that overlap in
+ * time on one GPU, from several threads or streams, race and their results
+ * are undefined; calls in sequence are safe, since each waits for its own work
+ * before returning. */
+#define TRIAD_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int triad_census_device_noalloc(int64_t n, int64_t nnz, const int64_t *csr_offsets, const int32_t *csr_nbrs,
+                                const uint8_t *dir_flags, const triad_opts *opts, void *hip_stream,
+                                uint64_t *d_out, uint64_t *h_out);
+
 /* Host-side validation of the input contract (no device needed). level 0 =
  * cheap checks, 1 = also symmetry and mirrored flags. Returns TRIAD_OK or the
  * error status the census would return. */

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1100,8 +1101,29 @@ struct Events {
   }
 };
 
+// Upper bound of the scratch bytes census_device takes from an arena for a
+// plain-schedule call (each request rounded up to 256 bytes): per row the
+// first-task index, task count and its scan, per entry the packed word and a
+// row-start bit, per task its word, N(v) count and hub-list slots, plus the
+// emission segment list and the scans' block sums.
+static size_t census_scratch_bound(int64_t n, int64_t nnz) {
+  const int64_t m = nnz / 2;
+  auto r = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) & ~(int64_t)255); };
+  size_t b = r(4) + r(20 * 8);
+  if (n > 0) {
+    b += r(4 * n) + r(8 * n) + r(8 * (n + 1)) + r(4 * ((nnz >> 5) + 1)) + r(4 * (nnz + PAD));
+    b += r(8 * ((n + SCAN_B - 1) / SCAN_B + 1));
+  }
+  if (m > 0) {
+    b += r(8 * m) + r(4 * m) + r(8 * m) + r(8 * m) + r(8 * (m + 1)) + r(8 * emit_seg_cap(n, m));
+    b += r(8 * ((m + SCAN_B - 1) / SCAN_B + 1));
+  }
+  return b;
+}
+
 int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
-                  const triad_opts* opts, hipStream_t s, uint64_t* d_out, uint64_t* h_out) {
+                  const triad_opts* opts, hipStream_t s, uint64_t* d_out, uint64_t* h_out, void* arena = nullptr,
+                  size_t arena_bytes = 0) {
   triad_opts o{};
   if (opts) o = *opts;
   if (n < 0 || n >= ((int64_t)1 << 30)) return fail(TRIAD_EINVAL, "n must be in [0, 2^30)");
@@ -1120,9 +1142,17 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   DeviceInfo di;
   if (int st = device_info(&di)) return st;
 
+  if (arena) {
+    if (o.schedule != TRIAD_SCHED_PLAIN || o.task_cycles || o.timing)
+      return fail(TRIAD_EINVAL, "the no-allocation census takes the plain schedule, no cycle recording and no timing");
+    const size_t need = census_scratch_bound(n, nnz);
+    if (need > arena_bytes)
+      return fail(TRIAD_EINVAL, "graph too large for the no-allocation census: it needs " + std::to_string(need) +
+                                    " bytes of scratch, the static scratch holds " + std::to_string(arena_bytes));
+  }
   Events ev;
   if (o.timing) HIPCHK(ev.init());
-  Scratch scratch(s);
+  Scratch scratch = arena ? Scratch(s, arena, arena_bytes) : Scratch(s);
   uint32_t* err = nullptr;
   unsigned long long* acc = nullptr;  // [16] census accumulators + [2] queue counters + [1] hub count
   ALLOC(err, 1);
@@ -1533,7 +1563,45 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
 
 using namespace triad;
 
+// Scratch of the no-allocation census: one copy per GPU, held until the
+// process ends. Host code never passes this name to a kernel (on the host it
+// is a stand-in, not a device address); it takes each device's address once
+// with hipGetSymbolAddress and uses that.
+static __device__ __align__(256) unsigned char scratch[TRIAD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[MAX_DEVICES] = {};
+
+// The calling thread's current device's copy of `scratch` (address taken on
+// the first call for that device, with it current).
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(TRIAD_EDEVICE, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TRIAD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return TRIAD_OK;
+}
+}  // namespace
+
 extern "C" {
+
+int triad_census_device_noalloc(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
+                                const triad_opts* opts, void* stream, uint64_t* d_out, uint64_t* h_out) {
+  void* base = nullptr;
+  if (int st = noalloc_scratch(&base)) return st;
+  return census_device(n, nnz, off, nbr, flg, opts, (hipStream_t)stream, d_out, h_out, base,
+                       (size_t)TRIAD_NOALLOC_SCRATCH_BYTES);
+}
 
 int triad_census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
                         const triad_opts* opts, void* stream, uint64_t* d_out, uint64_t* h_out) {

@@ -60,17 +60,30 @@ int device_info(DeviceInfo* out);
       return fail(TRIAD_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
-// Stream-ordered scratch memory, released (in stream order) on destruction.
+// Scratch memory of one call. By default stream-ordered allocations, released
+// (in stream order) on destruction. Given an arena (a caller-owned device
+// range), it hands out 256-byte aligned pieces of it instead and allocates
+// nothing; a request past the arena's end fails.
 struct Scratch {
   hipStream_t s;
   std::vector<void*> ptrs;
+  char* arena = nullptr;
+  size_t cap = 0, used = 0;
   explicit Scratch(hipStream_t st) : s(st) {}
+  Scratch(hipStream_t st, void* base, size_t bytes) : s(st), arena(static_cast<char*>(base)), cap(bytes) {}
   ~Scratch() {
     for (void* p : ptrs) (void)hipFreeAsync(p, s);
   }
   template <class T>
   hipError_t get(T** p, int64_t count) {
     size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    if (arena) {
+      const size_t at = (used + 255) & ~(size_t)255;
+      if (at > cap || bytes > cap - at) return hipErrorOutOfMemory;
+      *p = reinterpret_cast<T*>(arena + at);
+      used = at + bytes;
+      return hipSuccess;
+    }
     hipError_t e = hipMallocAsync((void**)p, bytes, s);
     if (e == hipSuccess) ptrs.push_back(*p);
     return e;

@@ -33,7 +33,7 @@ MLP_IN, MLP_HIDDEN = 6, 32
 MLP_PARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 
 EXPORTS = [
-    "triad_census", "triad_census_ex", "triad_census_device", "triad_validate_host",
+    "triad_census", "triad_census_ex", "triad_census_device", "triad_census_device_noalloc", "triad_validate_host",
     "triad_batch_plan_create", "triad_batch_plan_launch", "triad_batch_plan_status",
     "triad_batch_plan_destroy", "triad_census_batch", "triad_batch_autotune",
     "triad_csr_from_arcs", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
@@ -81,6 +81,7 @@ def lib():
             "triad_census": [i64, vp, vp, vp, vp],
             "triad_census_ex": [i64, vp, vp, vp, po, vp, vp],
             "triad_census_device": [i64, i64, vp, vp, vp, po, vp, vp, vp],
+            "triad_census_device_noalloc": [i64, i64, vp, vp, vp, po, vp, vp, vp],
             "triad_validate_host": [i64, vp, vp, vp, i32],
             "triad_batch_plan_create": [i32, i64, i64, vp, vp, vp, vp, vp, po, vp, ctypes.POINTER(vp)],
             "triad_batch_plan_launch": [vp, vp],
@@ -193,6 +194,18 @@ def triad_census_device(n, nnz, d_off, d_nbr, d_flg, stream=None, d_out=None, **
     st = _check(lib().triad_census_device(n, nnz, _tp(d_off), _tp(d_nbr), _tp(d_flg), ctypes.byref(o),
                                           _stream(stream), _tp(d_out), _p(h)))
     return _result(h, h[16]), st, tm.as_dict()
+
+
+def triad_census_device_noalloc(n, nnz, d_off, d_nbr, d_flg, d_out, stream=None, **kw):
+    """As triad_census_device, through the entry point that allocates nothing
+    (its scratch is the library's static device array). `d_out` (17 x 64-bit
+    on the device) is required: this path allocates no output either.
+    Returns (counts, status)."""
+    h = np.zeros(17, dtype=np.uint64)
+    o = make_opts(**kw)
+    st = _check(lib().triad_census_device_noalloc(n, nnz, _tp(d_off), _tp(d_nbr), _tp(d_flg), ctypes.byref(o),
+                                                  _stream(stream), _tp(d_out), _p(h)))
+    return _result(h, h[16]), st
 
 
 def to_device(g, device="cuda"):
