@@ -215,6 +215,33 @@ int triad_csr_from_arcs(int64_t n, int64_t narcs, const int32_t *d_src, const in
                         int64_t *d_offsets, int32_t *d_nbrs, uint8_t *d_flags, int64_t *nnz_out,
                         float *device_ms);
 
+/* ---------------------------------------------------- incremental census
+ * The census of a graph that changes over time, monitored at fixed intervals
+ * (Sec. 3, Figs. 3-4): given the graph before a batch of arc updates (DEVICE
+ * CSR as above) and its census census_in (HOST, 17 words: the 16 counts, then
+ * the high word of 003), returns in census_out (HOST, 17 words, same layout)
+ * the census after the batch, from the neighbour lists of the changed pairs
+ * only, and, if d_offsets_new is not NULL, writes the CSR after the batch.
+ * Update i (DEVICE arrays) inserts the arc d_src[i] -> d_dst[i] when
+ * d_insert[i] = 1 and deletes it when 0; updates apply in order (the last
+ * update of an arc decides; inserting a present arc or deleting an absent one
+ * changes nothing). Outputs of the new CSR (DEVICE, caller-allocated):
+ * d_offsets_new int64[n+1], d_nbrs_new int32 with room for nnz + 2*nupd
+ * entries, d_flags_new uint8 with room for ceil((nnz + 2*nupd)/4) bytes;
+ * *nnz_new (host) receives the new entry count. changed_pairs (host, may be
+ * NULL) receives the number of vertex pairs whose arcs changed. census_in
+ * must be the census of the input graph (it is not checked). Limits as for
+ * triad_census_device, nnz < 2^32, nupd < 2^31. Errors: TRIAD_EINVAL,
+ * TRIAD_ERANGE (an endpoint outside [0, n) or d_insert[i] > 1),
+ * TRIAD_ESELFLOOP (an update of a self-loop), TRIAD_ENOMEM; nothing is written
+ * on error. Returns TRIAD_OK_003_WRAPPED when the new 003 is >= 2^64. The
+ * call waits for its work on hip_stream before returning. */
+int triad_census_update(int64_t n, int64_t nnz, const int64_t *d_offsets, const int32_t *d_nbrs,
+                        const uint8_t *d_flags, int64_t nupd, const int32_t *d_src, const int32_t *d_dst,
+                        const uint8_t *d_insert, const uint64_t census_in[17], uint64_t census_out[17],
+                        int64_t *d_offsets_new, int32_t *d_nbrs_new, uint8_t *d_flags_new, int64_t *nnz_new,
+                        int64_t *changed_pairs, void *hip_stream);
+
 /* ------------------------------------------------------- learned schedule
  * Cost model: an FP32 multilayer perceptron 6 -> 32 -> 32 -> 1 with ReLU
  * hidden layers. Parameters, packed in this order: W1[32][6], b1[32],

@@ -23,6 +23,7 @@
 
 #include <string>
 
+#include "device_sort.h"
 #include "triad_internal.h"
 
 namespace triad {
@@ -230,6 +231,8 @@ __global__ void __launch_bounds__(SC_T) k_sc_apply(const uint32_t* __restrict__ 
     }
 }
 
+}  // namespace
+
 int scan_u32(const uint32_t* in, int64_t m, uint32_t* out, uint32_t* total, Scratch& scratch, hipStream_t s) {
   const int64_t nb = (m + SC_B - 1) / SC_B;
   uint32_t* bsum = nullptr;
@@ -242,6 +245,27 @@ int scan_u32(const uint32_t* in, int64_t m, uint32_t* out, uint32_t* total, Scra
   HIPCHK(hipGetLastError());
   return TRIAD_OK;
 }
+
+// Stable LSD radix sort of N 64-bit keys on bits [lo, hi), 8 bits per pass;
+// *keys points at the sorted keys on return (one of the two buffers).
+int radix_sort_u64(uint64_t** keys, uint64_t** tmp, int64_t N, int lo, int hi, Scratch& scratch, hipStream_t s) {
+  if (N >= ((int64_t)1 << 32)) return fail(TRIAD_EINVAL, "radix sort of 2^32 or more keys");
+  if (N == 0) return TRIAD_OK;
+  const int64_t ntiles = (N + RS_TILE - 1) / RS_TILE;
+  uint32_t *counts = nullptr, *offs = nullptr;
+  ALLOC(counts, (int64_t)RS_BUCKETS * ntiles);
+  ALLOC(offs, (int64_t)RS_BUCKETS * ntiles);
+  for (int shift = lo; shift < hi; shift += RS_BITS) {
+    k_rs_hist<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(*keys, N, shift, counts, ntiles);
+    if (int st = scan_u32(counts, (int64_t)RS_BUCKETS * ntiles, offs, nullptr, scratch, s)) return st;
+    k_rs_scatter<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(*keys, *tmp, N, shift, offs, ntiles);
+    HIPCHK(hipGetLastError());
+    std::swap(*keys, *tmp);
+  }
+  return TRIAD_OK;
+}
+
+namespace {
 
 // ------------------------------------------------------------ runs -> CSR
 __device__ __forceinline__ bool run_head(const uint64_t* key, int64_t i) {
@@ -339,12 +363,12 @@ __global__ void k_zero_words(uint32_t* p, int64_t m) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) p[i] = 0;
 }
 
+}  // namespace
+
 int grid_of(int64_t work, int threads, int cap) {
   int64_t g = (work + threads - 1) / threads;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
-
-}  // namespace
 
 int csr_from_arcs(int64_t n, int64_t narcs, const int32_t* src, const int32_t* dst, hipStream_t s, int64_t* off,
                   int32_t* nbr, uint8_t* flg, int64_t* nnz_out, float* ms_out) {
@@ -398,18 +422,7 @@ int csr_from_arcs(int64_t n, int64_t narcs, const int32_t* src, const int32_t* d
   HIPCHK(hipStreamSynchronize(s));
   if (errh) return fail(TRIAD_ERANGE, "arc endpoint outside [0, n)");
   // radix sort over bits [0, 2 + 2 rb): direction bit, column, row
-  const int64_t ntiles = (N + RS_TILE - 1) / RS_TILE;
-  uint32_t *counts = nullptr, *offs = nullptr;
-  ALLOC(counts, (int64_t)RS_BUCKETS * ntiles);
-  ALLOC(offs, (int64_t)RS_BUCKETS * ntiles);
-  const int bits = 2 + 2 * rb;
-  for (int shift = 0; shift < bits; shift += RS_BITS) {
-    k_rs_hist<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(ka, N, shift, counts, ntiles);
-    if (int st = scan_u32(counts, (int64_t)RS_BUCKETS * ntiles, offs, nullptr, scratch, s)) return st;
-    k_rs_scatter<<<(unsigned)ntiles, RS_THREADS, 0, s>>>(ka, kb, N, shift, offs, ntiles);
-    HIPCHK(hipGetLastError());
-    std::swap(ka, kb);
-  }
+  if (int st = radix_sort_u64(&ka, &kb, N, 0, 2 + 2 * rb, scratch, s)) return st;
   // runs of equal (row, col): one CSR entry each
   const int64_t nvalid = N - 2 * (int64_t)nloops;
   const int64_t vt = std::max<int64_t>(1, (nvalid + RS_TILE - 1) / RS_TILE);

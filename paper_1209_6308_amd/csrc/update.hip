@@ -1,0 +1,581 @@
+// Incremental census of a graph that changes by arc insertions and deletions:
+// the census of the graph after a batch of updates, from the census before it
+// and a merge of the neighbour lists of each changed pair only (the census at
+// fixed time intervals of Sec. 3, Figs. 3-4, without a full sweep per
+// interval).
+//
+// A batch is a sequence of arc operations applied in order (insert x->y, or
+// delete it). Only its net effect on each unordered pair {a, b}, a < b,
+// matters: the pair's flag f (bit0 = a->b, bit1 = b->a, as in row a of the
+// CSR) goes from f0 to f1, each bit being set by the last operation on its arc
+// (or kept). Only triads that contain a changed pair change class, and
+//     census(after) - census(before)
+//       = sum over changed pairs {a, b}, over third vertices w, of
+//         [class after] - [class before] of the triad {a, b, w},
+// each triad counted by the smallest of its changed pairs (pair order
+// a << RB | b). For one changed pair the third vertices are
+//   - w in N(a) or N(b), before or after: the triad's code is read from the
+//     two rows (and the changed pairs of a and b), before and after;
+//   - every other w (n - 2 - |that union| of them): only the pair {a, b} has
+//     arcs, so the triad moves from the dyadic class of f0 to that of f1
+//     (Fig. 5 steps 2.1.2-2.1.3 for a single edge).
+// The classes come from the 64-state table of the census (Fig. 5 step
+// 2.1.4.1). The null count stays C(n,3) minus the rest.
+//
+//   k_upd_keys      one key per operation: pair, arc direction, kind
+//   radix sort      by (pair, direction), stable: operations keep their order
+//   k_run_heads     first operation of each pair
+//   k_pair_state    f0 from the CSR, f1 from the last operation on each arc
+//   k_changed_keys  two entries per changed pair (one per row), sorted
+//   k_upd_delta     one wavefront per changed pair: the class changes
+//   k_row_marks, k_new_offsets, k_copy_old, k_insert_new, k_pack_bytes
+//                   the CSR after the batch
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "device_sort.h"
+#include "triad_internal.h"
+
+namespace triad {
+namespace {
+
+constexpr int UT = 256;
+
+__device__ __forceinline__ uint32_t mirror2(uint32_t f) { return ((f & 1u) << 1) | (f >> 1); }
+__device__ __forceinline__ uint32_t entry_flag(const uint8_t* flg, int64_t j) {
+  return (flg[j >> 2] >> (2 * (j & 3))) & 3u;
+}
+
+// first position in nbr[b, e) with an id >= y
+__device__ __forceinline__ int64_t lower_id(const int32_t* nbr, int64_t b, int64_t e, int32_t y) {
+  while (b < e) {
+    const int64_t m = (b + e) >> 1;
+    if (nbr[m] < y) b = m + 1; else e = m;
+  }
+  return b;
+}
+
+// first position in keys[b, e) whose key is >= k
+__device__ __forceinline__ int64_t lower_key(const uint64_t* keys, int64_t b, int64_t e, uint64_t k) {
+  while (b < e) {
+    const int64_t m = (b + e) >> 1;
+    if (keys[m] < k) b = m + 1; else e = m;
+  }
+  return b;
+}
+
+// Operation key: (a << rb | b) << 2 | dir << 1 | insert, a < b the pair, dir =
+// 1 for the arc b -> a.
+__global__ void k_upd_keys(int64_t n, int64_t k, int rb, const int32_t* __restrict__ src,
+                           const int32_t* __restrict__ dst, const uint8_t* __restrict__ ins,
+                           uint64_t* __restrict__ keys, uint32_t* __restrict__ err) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  uint32_t bits = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride) {
+    const int32_t s = src[i], d = dst[i];
+    const uint32_t op = ins[i];
+    if (s < 0 || d < 0 || s >= n || d >= n || op > 1u) {
+      bits |= ERR_RANGE;
+      keys[i] = 0;
+      continue;
+    }
+    if (s == d) bits |= ERR_SELFLOOP;
+    const uint64_t a = (uint64_t)min(s, d), b = (uint64_t)max(s, d);
+    keys[i] = (((a << rb) | b) << 2) | ((uint64_t)(s > d) << 1) | op;
+  }
+  if (bits) atomicOr(err, bits);
+}
+
+__global__ void k_run_heads(const uint64_t* __restrict__ keys, int64_t k, int shift, uint32_t* __restrict__ head) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride)
+    head[i] = (i == 0 || (keys[i] >> shift) != (keys[i - 1] >> shift)) ? 1u : 0u;
+}
+
+// Per pair (run of operations): f0 from row a of the CSR, f1 = f0 with each
+// arc's bit set by the last operation on that arc (runs are sorted by arc
+// direction, operations in batch order within it).
+__global__ void k_pair_state(const uint64_t* __restrict__ keys, int64_t k, int rb, const uint32_t* __restrict__ head,
+                             const uint32_t* __restrict__ hpos, const int64_t* __restrict__ off,
+                             const int32_t* __restrict__ nbr, const uint8_t* __restrict__ flg,
+                             uint64_t* __restrict__ pkey, uint8_t* __restrict__ pf, uint32_t* __restrict__ chg) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t bmask = (1ull << rb) - 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride) {
+    if (!head[i]) continue;
+    const uint64_t pr = keys[i] >> 2;
+    const int64_t a = (int64_t)(pr >> rb);
+    const int32_t b = (int32_t)(pr & bmask);
+    const int64_t e = off[a + 1];
+    const int64_t j = lower_id(nbr, off[a], e, b);
+    const uint32_t f0 = (j < e && nbr[j] == b) ? entry_flag(flg, j) : 0u;
+    uint32_t f1 = f0;
+    for (int64_t q = i; q < k && (keys[q] >> 2) == pr; ++q) {
+      const uint32_t bit = 1u << ((keys[q] >> 1) & 1u);
+      f1 = (keys[q] & 1u) ? (f1 | bit) : (f1 & ~bit);
+    }
+    const uint32_t r = hpos[i];
+    pkey[r] = pr;
+    pf[r] = (uint8_t)(f0 | f1 << 2);
+    chg[r] = f0 != f1 ? 1u : 0u;
+  }
+}
+
+// Two entries per changed pair, one in each row: (row << rb | col) << 4 |
+// f0 << 2 | f1, flags seen from the row (mirrored in row b).
+__global__ void k_changed_keys(const uint64_t* __restrict__ pkey, const uint8_t* __restrict__ pf,
+                               const uint32_t* __restrict__ chg, const uint32_t* __restrict__ cpos, int64_t np,
+                               int rb, uint64_t* __restrict__ E) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t bmask = (1ull << rb) - 1;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < np; r += stride) {
+    if (!chg[r]) continue;
+    const uint64_t a = pkey[r] >> rb, b = pkey[r] & bmask;
+    const uint32_t f0 = pf[r] & 3u, f1 = pf[r] >> 2;
+    const uint32_t c = cpos[r];
+    E[2 * (int64_t)c] = (((a << rb) | b) << 4) | (f0 << 2) | f1;
+    E[2 * (int64_t)c + 1] = (((b << rb) | a) << 4) | (mirror2(f0) << 2) | mirror2(f1);
+  }
+}
+
+struct DeltaArgs {
+  int64_t n;
+  const int64_t* off;
+  const int32_t* nbr;
+  const uint8_t* flg;
+  int rb;
+  const uint64_t* E;  // sorted change entries
+  int64_t nE;
+  uint64_t lut[4];    // class of code c: nibble c & 15 of lut[c >> 4]
+  unsigned long long* delta;  // [16], two's complement
+};
+
+__device__ __forceinline__ uint32_t class_of(const DeltaArgs& g, uint32_t code) {
+  const uint64_t w = code < 16 ? g.lut[0] : code < 32 ? g.lut[1] : code < 48 ? g.lut[2] : g.lut[3];
+  return (uint32_t)(w >> (4 * (code & 15u))) & 15u;
+}
+
+// Change entry of (x, y) in E[b, e) (the row x range): index or -1.
+__device__ __forceinline__ int64_t find_change(const DeltaArgs& g, int64_t b, int64_t e, int64_t x, int32_t y) {
+  const uint64_t k = (((uint64_t)x << g.rb) | (uint64_t)y) << 4;
+  const int64_t p = lower_key(g.E, b, e, k);
+  return (p < e && (g.E[p] >> 4) == (k >> 4)) ? p : -1;
+}
+
+// One wavefront per changed pair {a, b} (the entries of row a in E). The third
+// vertices are taken from four sorted lists: N(a), the changes of a, N(b), the
+// changes of b; a vertex seen in an earlier list is skipped in a later one.
+__global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
+  __shared__ int32_t hist[UT / 64][16][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int32_t* h = &hist[wv][0][0];
+  for (int c = 0; c < 16; ++c) h[c * 64 + lane] = 0;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const uint64_t cmask = (1ull << g.rb) - 1;
+  uint32_t steps = 0;
+  for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < g.nE; q += nw) {
+    const uint64_t ent = g.E[q];
+    const int64_t a = (int64_t)(ent >> (4 + g.rb));
+    const int32_t b = (int32_t)((ent >> 4) & cmask);
+    if (b < a) continue;  // the pair is processed from its lower row
+    const uint32_t f0 = (ent >> 2) & 3u, f1 = ent & 3u;
+    const uint64_t pk = ((uint64_t)a << g.rb) | (uint64_t)b;
+    const int64_t oa = g.off[a], ea = g.off[a + 1], ob = g.off[b], eb = g.off[b + 1];
+    const int64_t da0 = lower_key(g.E, 0, g.nE, (uint64_t)a << (g.rb + 4));
+    const int64_t da1 = lower_key(g.E, da0, g.nE, (uint64_t)(a + 1) << (g.rb + 4));
+    const int64_t db0 = lower_key(g.E, 0, g.nE, (uint64_t)b << (g.rb + 4));
+    const int64_t db1 = lower_key(g.E, db0, g.nE, (uint64_t)(b + 1) << (g.rb + 4));
+    uint32_t ucount = 0;
+    for (int phase = 0; phase < 4; ++phase) {
+      const int64_t L0 = phase == 0 ? oa : phase == 1 ? da0 : phase == 2 ? ob : db0;
+      const int64_t L1 = phase == 0 ? ea : phase == 1 ? da1 : phase == 2 ? eb : db1;
+      for (int64_t j0 = L0; j0 < L1; j0 += 64) {
+        const int64_t j = j0 + lane;
+        if (j >= L1) continue;
+        int32_t w;
+        uint32_t g0a = 0, g1a = 0, g0b = 0, g1b = 0;
+        bool cha = false, chb = false, keep = true;
+        if (phase == 0 || phase == 2) {
+          w = g.nbr[j];
+          if (w == a || w == b) continue;
+          const uint32_t f = entry_flag(g.flg, j);
+          if (phase == 0) {
+            g0a = f;
+            const int64_t p = find_change(g, da0, da1, a, w);
+            cha = p >= 0;
+            g1a = cha ? (uint32_t)(g.E[p] & 3u) : g0a;
+          } else {
+            g0b = f;
+            // seen in N(a) or in the changes of a already?
+            const int64_t ja = lower_id(g.nbr, oa, ea, w);
+            keep = !(ja < ea && g.nbr[ja] == w) && find_change(g, da0, da1, a, w) < 0;
+            g0a = g1a = 0;
+          }
+          if (keep) {
+            if (phase == 0) {
+              const int64_t jb = lower_id(g.nbr, ob, eb, w);
+              g0b = (jb < eb && g.nbr[jb] == w) ? entry_flag(g.flg, jb) : 0u;
+            }
+            const int64_t p = find_change(g, db0, db1, b, w);
+            chb = p >= 0;
+            g1b = chb ? (uint32_t)(g.E[p] & 3u) : g0b;
+          }
+        } else {
+          const uint64_t e = g.E[j];
+          w = (int32_t)((e >> 4) & cmask);
+          if (w == a || w == b) continue;
+          if (phase == 1) {
+            g0a = (e >> 2) & 3u;
+            g1a = e & 3u;
+            cha = true;
+            keep = g0a == 0;  // otherwise w is in N(a), seen in phase 0
+            if (keep) {
+              const int64_t jb = lower_id(g.nbr, ob, eb, w);
+              g0b = (jb < eb && g.nbr[jb] == w) ? entry_flag(g.flg, jb) : 0u;
+              const int64_t p = find_change(g, db0, db1, b, w);
+              chb = p >= 0;
+              g1b = chb ? (uint32_t)(g.E[p] & 3u) : g0b;
+            }
+          } else {
+            g0b = (e >> 2) & 3u;
+            g1b = e & 3u;
+            chb = true;
+            if (g0b != 0) {
+              keep = false;  // in N(b), seen in phase 2
+            } else {
+              const int64_t ja = lower_id(g.nbr, oa, ea, w);
+              keep = !(ja < ea && g.nbr[ja] == w) && find_change(g, da0, da1, a, w) < 0;
+            }
+          }
+        }
+        if (!keep) continue;
+        ++ucount;
+        // the triad is counted by the smallest of its changed pairs
+        bool own = true;
+        if (cha) own = own && pk < ((((uint64_t)min((int64_t)w, a)) << g.rb) | (uint64_t)max((int64_t)w, a));
+        if (chb) own = own && pk < ((((uint64_t)min(w, b)) << g.rb) | (uint64_t)max(w, b));
+        if (!own) continue;
+        const uint32_t oc = class_of(g, f0 | g0a << 2 | g0b << 4), nc = class_of(g, f1 | g1a << 2 | g1b << 4);
+        if (oc != nc) {
+          h[oc * 64 + lane] -= 1;
+          h[nc * 64 + lane] += 1;
+        }
+      }
+    }
+    // every other third vertex: only the pair {a, b} has arcs
+    uint32_t u = ucount;
+    for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o, 64);
+    if (lane == 0) {
+      const int64_t rest = g.n - 2 - (int64_t)u;
+      const uint32_t oc = class_of(g, f0), nc = class_of(g, f1);
+      if (rest > 0 && oc != nc) {
+        atomicAdd(&g.delta[oc], (unsigned long long)(-rest));
+        atomicAdd(&g.delta[nc], (unsigned long long)rest);
+      }
+    }
+    steps += (uint32_t)((ea - oa + eb - ob + da1 - da0 + db1 - db0) / 64 + 4);
+    if (steps > (1u << 29)) {
+      __builtin_amdgcn_wave_barrier();
+      for (int c = 0; c < 16; ++c) {
+        int64_t x = h[c * 64 + lane];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0 && x) atomicAdd(&g.delta[c], (unsigned long long)x);
+        h[c * 64 + lane] = 0;
+      }
+      steps = 0;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int c = 0; c < 16; ++c) {
+    int64_t x = h[c * 64 + lane];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0 && x) atomicAdd(&g.delta[c], (unsigned long long)x);
+  }
+}
+
+// ---------------------------------------------------------- CSR after
+// Change entry e is an insertion (f0 = 0), a deletion (f1 = 0) or a new flag.
+__global__ void k_change_kinds(const uint64_t* __restrict__ E, int64_t nE, uint32_t* __restrict__ ins,
+                               uint32_t* __restrict__ del) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= nE; e += stride) {
+    const uint32_t f0 = e < nE ? (uint32_t)(E[e] >> 2) & 3u : 1u, f1 = e < nE ? (uint32_t)E[e] & 3u : 1u;
+    ins[e] = f0 == 0 ? 1u : 0u;
+    del[e] = f1 == 0 ? 1u : 0u;
+  }
+}
+
+__global__ void k_row_marks(const uint64_t* __restrict__ E, int64_t nE, int rb, uint32_t* __restrict__ mark) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nE; e += stride) {
+    const uint64_t x = E[e] >> (4 + rb);
+    atomicOr(&mark[x >> 5], 1u << (x & 31));
+  }
+}
+
+// new_off[x] = off[x] + insertions - deletions in rows below x
+__global__ void k_new_offsets(int64_t n, int rb, const int64_t* __restrict__ off, const uint64_t* __restrict__ E,
+                              int64_t nE, const uint32_t* __restrict__ I, const uint32_t* __restrict__ D,
+                              int64_t* __restrict__ noff) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= n; x += stride) {
+    const int64_t e = lower_key(E, 0, nE, (uint64_t)x << (rb + 4));
+    noff[x] = off[x] + (int64_t)I[e] - (int64_t)D[e];
+  }
+}
+
+constexpr int COPY_TILE = 4096;
+
+// Old entries to their new places: rows without changes shift as a whole;
+// in a changed row an entry moves by the insertions and deletions before it,
+// takes its new flag, or is dropped.
+__global__ void __launch_bounds__(UT) k_copy_old(int64_t n, int64_t nnz, int rb, const int64_t* __restrict__ off,
+                                                 const int32_t* __restrict__ nbr, const uint8_t* __restrict__ flg,
+                                                 const uint64_t* __restrict__ E, int64_t nE,
+                                                 const uint32_t* __restrict__ I, const uint32_t* __restrict__ D,
+                                                 const uint32_t* __restrict__ mark, const int64_t* __restrict__ noff,
+                                                 int64_t nn, int32_t* __restrict__ nnbr, uint8_t* __restrict__ nfl) {
+  __shared__ int64_t rr[2];
+  for (int64_t t0 = (int64_t)blockIdx.x * COPY_TILE; t0 < nnz; t0 += (int64_t)gridDim.x * COPY_TILE) {
+    const int64_t t1 = min(t0 + COPY_TILE, nnz);
+    __syncthreads();
+    if (threadIdx.x < 2) {
+      // row of entry t0 / t1 - 1: last x with off[x] <= j
+      const int64_t j = threadIdx.x == 0 ? t0 : t1 - 1;
+      int64_t lo = 0, hi = n;
+      while (hi - lo > 1) {
+        const int64_t m = (lo + hi) >> 1;
+        if (off[m] <= j) lo = m; else hi = m;
+      }
+      rr[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const int64_t r0 = rr[0], r1 = rr[1];
+    for (int64_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
+      int64_t lo = r0, hi = r1 + 1;
+      while (hi - lo > 1) {
+        const int64_t m = (lo + hi) >> 1;
+        if (off[m] <= j) lo = m; else hi = m;
+      }
+      const int64_t x = lo;
+      const int32_t y = nbr[j];
+      uint32_t f = entry_flag(flg, j);
+      int64_t pos = noff[x] + (j - off[x]);
+      if ((mark[x >> 5] >> (x & 31)) & 1u) {
+        const int64_t ex = lower_key(E, 0, nE, (uint64_t)x << (rb + 4));
+        const uint64_t k = (((uint64_t)x << rb) | (uint64_t)y) << 4;
+        const int64_t e = lower_key(E, ex, nE, k);
+        pos += ((int64_t)I[e] - (int64_t)I[ex]) - ((int64_t)D[e] - (int64_t)D[ex]);
+        if (e < nE && (E[e] >> 4) == (k >> 4)) {
+          f = (uint32_t)E[e] & 3u;
+          if (f == 0) continue;  // deleted
+        }
+      }
+      if (pos >= 0 && pos < nn) {  // always true; keeps a faulty position in bounds
+        nnbr[pos] = y;
+        nfl[pos] = (uint8_t)f;
+      }
+    }
+  }
+}
+
+__global__ void k_insert_new(int rb, const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                             const uint64_t* __restrict__ E, int64_t nE, const uint32_t* __restrict__ I,
+                             const uint32_t* __restrict__ D, const int64_t* __restrict__ noff, int64_t nn,
+                             int32_t* __restrict__ nnbr, uint8_t* __restrict__ nfl) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t cmask = (1ull << rb) - 1;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nE; e += stride) {
+    if (((E[e] >> 2) & 3u) != 0) continue;  // not an insertion
+    const int64_t x = (int64_t)(E[e] >> (4 + rb));
+    const int32_t y = (int32_t)((E[e] >> 4) & cmask);
+    const int64_t ex = lower_key(E, 0, nE, (uint64_t)x << (rb + 4));
+    const int64_t below = lower_id(nbr, off[x], off[x + 1], y) - off[x];
+    const int64_t pos = noff[x] + below + ((int64_t)I[e] - (int64_t)I[ex]) - ((int64_t)D[e] - (int64_t)D[ex]);
+    if (pos >= 0 && pos < nn) {
+      nnbr[pos] = y;
+      nfl[pos] = (uint8_t)(E[e] & 3u);
+    }
+  }
+}
+
+__global__ void k_pack_bytes(const uint8_t* __restrict__ f, int64_t m, uint8_t* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x, nb = (m + 3) / 4;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += stride) {
+    uint32_t v = 0;
+    for (int k = 0; k < 4; ++k)
+      if (4 * b + k < m) v |= (uint32_t)(f[4 * b + k] & 3u) << (2 * k);
+    out[b] = (uint8_t)v;
+  }
+}
+
+__global__ void k_zero32(uint32_t* p, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) p[i] = 0;
+}
+
+__global__ void k_copy_words(const uint32_t* __restrict__ a, uint32_t* __restrict__ b, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) b[i] = a[i];
+}
+__global__ void k_copy_bytes(const uint8_t* __restrict__ a, uint8_t* __restrict__ b, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) b[i] = a[i];
+}
+__global__ void k_copy_i64(const int64_t* __restrict__ a, int64_t* __restrict__ b, int64_t m) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) b[i] = a[i];
+}
+
+}  // namespace
+
+int census_update(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg, int64_t k,
+                  const int32_t* src, const int32_t* dst, const uint8_t* ins, const uint64_t* cin, uint64_t* cout,
+                  int64_t* noff, int32_t* nnbr, uint8_t* nflg, int64_t* nnz_new, int64_t* changed_pairs,
+                  hipStream_t s) {
+  if (n < 0 || n >= ((int64_t)1 << 30)) return fail(TRIAD_EINVAL, "n must be in [0, 2^30)");
+  if (nnz < 0 || nnz >= ((int64_t)1 << 32)) return fail(TRIAD_EINVAL, "nnz must be in [0, 2^32)");
+  if (k < 0 || k >= ((int64_t)1 << 31)) return fail(TRIAD_EINVAL, "the update count must be in [0, 2^31)");
+  if (!off || !cin || !cout || (nnz > 0 && (!nbr || !flg)) || (k > 0 && (!src || !dst || !ins)))
+    return fail(TRIAD_EINVAL, "NULL pointer argument");
+  const bool new_csr = noff != nullptr;
+  if (new_csr && (!nnz_new || !nnbr || !nflg)) return fail(TRIAD_EINVAL, "NULL pointer for the new CSR");
+  Scratch scratch(s);
+  const int rb = std::max(1, 64 - __builtin_clzll((unsigned long long)std::max<int64_t>(n, 1)));
+  uint32_t* err = nullptr;
+  unsigned long long* delta = nullptr;
+  uint32_t* tot = nullptr;
+  ALLOC(err, 1);
+  ALLOC(delta, 16);
+  ALLOC(tot, 4);
+  k_zero32<<<1, 64, 0, s>>>(err, 1);
+  k_zero32<<<1, 64, 0, s>>>((uint32_t*)delta, 32);
+  k_zero32<<<1, 64, 0, s>>>(tot, 4);
+  int64_t np = 0, K = 0;
+  uint64_t* E = nullptr;
+  if (k > 0) {
+    uint64_t *ka = nullptr, *kb = nullptr;
+    ALLOC(ka, k);
+    ALLOC(kb, k);
+    k_upd_keys<<<grid_of(k, 256, 65536), 256, 0, s>>>(n, k, rb, src, dst, ins, ka, err);
+    uint32_t eh = 0;
+    HIPCHK(hipMemcpyAsync(&eh, err, sizeof eh, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (eh) return fail(status_from_bits(eh), eh & ERR_RANGE ? "update endpoint outside [0, n) or kind not 0/1"
+                                                             : "update on a self-loop");
+    // by (pair, direction); operations keep their batch order within an arc
+    if (int st = radix_sort_u64(&ka, &kb, k, 1, 2 + 2 * rb, scratch, s)) return st;
+    uint32_t *head = nullptr, *hpos = nullptr;
+    ALLOC(head, k);
+    ALLOC(hpos, k);
+    k_run_heads<<<grid_of(k, 256, 65536), 256, 0, s>>>(ka, k, 2, head);
+    if (int st = scan_u32(head, k, hpos, tot, scratch, s)) return st;
+    uint32_t h = 0;
+    HIPCHK(hipMemcpyAsync(&h, tot, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    np = h;
+    uint64_t* pkey = nullptr;
+    uint8_t* pf = nullptr;
+    uint32_t *chg = nullptr, *cpos = nullptr;
+    ALLOC(pkey, np);
+    ALLOC(pf, np);
+    ALLOC(chg, np);
+    ALLOC(cpos, np);
+    k_pair_state<<<grid_of(k, 256, 65536), 256, 0, s>>>(ka, k, rb, head, hpos, off, nbr, flg, pkey, pf, chg);
+    if (int st = scan_u32(chg, np, cpos, tot + 1, scratch, s)) return st;
+    HIPCHK(hipMemcpyAsync(&h, tot + 1, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    K = h;
+    if (K > 0) {
+      uint64_t* Eb = nullptr;
+      ALLOC(E, 2 * K);
+      ALLOC(Eb, 2 * K);
+      k_changed_keys<<<grid_of(np, 256, 65536), 256, 0, s>>>(pkey, pf, chg, cpos, np, rb, E);
+      if (int st = radix_sort_u64(&E, &Eb, 2 * K, 4, 4 + 2 * rb, scratch, s)) return st;
+      DeltaArgs g{};
+      g.n = n;
+      g.off = off;
+      g.nbr = nbr;
+      g.flg = flg;
+      g.rb = rb;
+      g.E = E;
+      g.nE = 2 * K;
+      for (int c = 0; c < 64; ++c) g.lut[c >> 4] |= (uint64_t)classify_code((unsigned)c) << (4 * (c & 15));
+      g.delta = delta;
+      k_upd_delta<<<grid_of(2 * K * 64, UT, 8192), UT, 0, s>>>(g);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  // the census after the batch
+  uint64_t dh[16];
+  HIPCHK(hipMemcpyAsync(dh, delta, sizeof dh, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  uint64_t res[17];
+  unsigned __int128 sum = 0;
+  for (int t = 1; t < 16; ++t) {
+    res[t] = cin[t] + dh[t];
+    sum += res[t];
+  }
+  uint64_t clo, chi;
+  choose3(n, &clo, &chi);
+  const unsigned __int128 nul = (((unsigned __int128)chi << 64) | clo) - sum;
+  res[0] = (uint64_t)nul;
+  res[16] = (uint64_t)(nul >> 64);
+  // the CSR after the batch
+  int64_t nn = nnz;
+  if (new_csr) {
+    if (K == 0) {
+      k_copy_i64<<<grid_of(n + 1, 256, 65536), 256, 0, s>>>(off, noff, n + 1);
+      if (nnz > 0) {
+        k_copy_words<<<grid_of(nnz, 256, 65536), 256, 0, s>>>((const uint32_t*)nbr, (uint32_t*)nnbr, nnz);
+        k_copy_bytes<<<grid_of((nnz + 3) / 4, 256, 65536), 256, 0, s>>>(flg, nflg, (nnz + 3) / 4);
+      }
+    } else {
+      const int64_t nE = 2 * K;
+      uint32_t *ik = nullptr, *dk = nullptr, *I = nullptr, *D = nullptr, *mark = nullptr;
+      uint8_t* nf8 = nullptr;
+      ALLOC(ik, nE + 1);
+      ALLOC(dk, nE + 1);
+      ALLOC(I, nE + 1);
+      ALLOC(D, nE + 1);
+      ALLOC(mark, (n >> 5) + 1);
+      k_change_kinds<<<grid_of(nE + 1, 256, 65536), 256, 0, s>>>(E, nE, ik, dk);
+      if (int st = scan_u32(ik, nE + 1, I, tot + 2, scratch, s)) return st;
+      if (int st = scan_u32(dk, nE + 1, D, tot + 3, scratch, s)) return st;
+      uint32_t idt[2];
+      HIPCHK(hipMemcpyAsync(idt, tot + 2, sizeof idt, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      nn = nnz + (int64_t)idt[0] - (int64_t)idt[1];
+      ALLOC(nf8, nn);
+      k_zero32<<<grid_of((n >> 5) + 1, 256, 4096), 256, 0, s>>>(mark, (n >> 5) + 1);
+      k_row_marks<<<grid_of(nE, 256, 65536), 256, 0, s>>>(E, nE, rb, mark);
+      k_new_offsets<<<grid_of(n + 1, 256, 65536), 256, 0, s>>>(n, rb, off, E, nE, I, D, noff);
+      if (nnz > 0)
+        k_copy_old<<<grid_of(nnz, COPY_TILE, 65536), UT, 0, s>>>(n, nnz, rb, off, nbr, flg, E, nE, I, D, mark, noff,
+                                                                 nn, nnbr, nf8);
+      k_insert_new<<<grid_of(nE, 256, 65536), 256, 0, s>>>(rb, off, nbr, E, nE, I, D, noff, nn, nnbr, nf8);
+      k_pack_bytes<<<grid_of((nn + 3) / 4, 256, 65536), 256, 0, s>>>(nf8, nn, nflg);
+      HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    *nnz_new = nn;
+  }
+  std::memcpy(cout, res, sizeof res);
+  if (changed_pairs) *changed_pairs = K;
+  return res[16] ? TRIAD_OK_003_WRAPPED : TRIAD_OK;
+}
+
+}  // namespace triad
+
+using namespace triad;
+
+extern "C" int triad_census_update(int64_t n, int64_t nnz, const int64_t* d_offsets, const int32_t* d_nbrs,
+                                   const uint8_t* d_flags, int64_t nupd, const int32_t* d_src, const int32_t* d_dst,
+                                   const uint8_t* d_insert, const uint64_t census_in[17], uint64_t census_out[17],
+                                   int64_t* d_offsets_new, int32_t* d_nbrs_new, uint8_t* d_flags_new,
+                                   int64_t* nnz_new, int64_t* changed_pairs, void* hip_stream) {
+  return census_update(n, nnz, d_offsets, d_nbrs, d_flags, nupd, d_src, d_dst, d_insert, census_in, census_out,
+                       d_offsets_new, d_nbrs_new, d_flags_new, nnz_new, changed_pairs, (hipStream_t)hip_stream);
+}

@@ -36,7 +36,7 @@ EXPORTS = [
     "triad_census", "triad_census_ex", "triad_census_device", "triad_census_device_noalloc", "triad_validate_host",
     "triad_batch_plan_create", "triad_batch_plan_launch", "triad_batch_plan_status",
     "triad_batch_plan_destroy", "triad_census_batch", "triad_batch_autotune",
-    "triad_csr_from_arcs", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
+    "triad_csr_from_arcs", "triad_census_update", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
     "triad_mlp_train", "triad_last_error", "triad_version",
 ]
 
@@ -91,6 +91,8 @@ def lib():
             "triad_batch_autotune": [i32, i64, i64, vp, vp, vp, vp, vp, ctypes.c_char_p, po],
             "triad_csr_from_arcs": [i64, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64),
                                     ctypes.POINTER(ctypes.c_float)],
+            "triad_census_update": [i64, i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp,
+                                    ctypes.POINTER(i64), ctypes.POINTER(i64), vp],
             "triad_task_features": [i64, i64, vp, vp, vp, vp, ctypes.POINTER(i64)],
             "triad_mlp_forward": [vp, vp, i64, vp, vp],
             "triad_mlp_loss_grad": [vp, vp, vp, i64, vp, vp, vp],
@@ -234,6 +236,37 @@ def csr_from_arcs(n, d_src, d_dst, stream=None, timed=False):
     k = int(nnz.value)
     out = (off, nbr[:k], flg[:(k + 3) // 4])
     return out + (float(ms.value),) if timed else out
+
+
+def census_update(n, nnz, d_off, d_nbr, d_flg, census, d_src, d_dst, d_ins, new_csr=True, stream=None):
+    """Census after a batch of arc updates (insert when d_ins[i] = 1, delete
+    when 0, in order) from `census` (16 Python ints) of the graph before it.
+    Returns (census after, (offsets, ids, flags) of the graph after or None,
+    number of changed pairs)."""
+    import torch
+    k = int(d_src.numel())
+    cin = np.zeros(17, dtype=np.uint64)
+    c0 = int(census[0])
+    cin[0] = c0 & ((1 << 64) - 1)
+    cin[16] = c0 >> 64
+    cin[1:16] = np.array([int(x) for x in census[1:16]], dtype=np.uint64)
+    cout = np.zeros(17, dtype=np.uint64)
+    nn = ctypes.c_int64(0)
+    chg = ctypes.c_int64(0)
+    out = None
+    dev = d_off.device
+    if new_csr:
+        cap = nnz + 2 * k
+        out = (torch.empty(n + 1, dtype=torch.int64, device=dev), torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+               torch.empty(max((cap + 3) // 4, 1), dtype=torch.uint8, device=dev))
+    _check(lib().triad_census_update(n, nnz, _tp(d_off), _tp(d_nbr), _tp(d_flg), k, _tp(d_src), _tp(d_dst),
+                                     _tp(d_ins), _p(cin), _p(cout), _tp(out[0]) if out else None,
+                                     _tp(out[1]) if out else None, _tp(out[2]) if out else None,
+                                     ctypes.byref(nn), ctypes.byref(chg), _stream(stream)))
+    if out:
+        m = int(nn.value)
+        out = (out[0], out[1][:m], out[2][:(m + 3) // 4])
+    return _result(cout, cout[16]), out, int(chg.value)
 
 
 # ------------------------------------------------------------------ batches

@@ -1,0 +1,130 @@
+"""Incremental census (arc insertions and deletions in batches, Sec. 3)
+against the oracle: after each batch the census equals the oracle's census of
+the updated arc set, bit-exact, and the CSR after the batch equals the host
+builder's, byte for byte."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.update import apply_updates
+from paper_1209_6308_amd import graphs, triad
+
+from _helpers import random_digraph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    t = pytest.importorskip("torch")
+    if not t.cuda.is_available():
+        pytest.skip("no HIP device")
+    return t
+
+
+def _random_batch(rng, n, src, dst, k, p_delete=0.4, p_reverse=0.2):
+    """k updates: deletions of existing arcs, insertions of reverse arcs of
+    existing ones (pairs turning mutual), insertions between random vertices,
+    and repeats of earlier updates (so some arcs get several operations)."""
+    us, ud, ui = [], [], []
+    m = src.size
+    for _ in range(k):
+        r = rng.random()
+        if m and r < p_delete:
+            i = rng.integers(m)
+            us.append(src[i]); ud.append(dst[i]); ui.append(0)
+        elif m and r < p_delete + p_reverse:
+            i = rng.integers(m)
+            us.append(dst[i]); ud.append(src[i]); ui.append(1)
+        elif us and r < 0.9:
+            a, b = rng.integers(n), rng.integers(n)
+            if a == b:
+                b = (a + 1) % n
+            us.append(a); ud.append(b); ui.append(1)
+        else:
+            j = rng.integers(len(us)) if us else None
+            if j is None:
+                a, b = 0, 1 % n
+                us.append(a); ud.append(b); ui.append(1)
+            else:
+                us.append(us[j]); ud.append(ud[j]); ui.append(1 - ui[j])
+    return np.array(us, np.int32), np.array(ud, np.int32), np.array(ui, np.uint8)
+
+
+def _run_series(torch, n, src, dst, batches, seed):
+    rng = np.random.default_rng(seed)
+    g = graphs.build_csr(n, src, dst)
+    s, d = g.arcs()
+    census = oracle.census(g)
+    dev = triad.to_device(g)
+    nnz = g.nnz
+    for k in batches:
+        us, ud, ui = _random_batch(rng, n, s, d, k)
+        t = [torch.from_numpy(a).cuda() for a in (us, ud, ui)]
+        got, new, changed = triad.census_update(n, nnz, *dev, census, *t)
+        s, d = apply_updates(s, d, us, ud, ui)
+        want_g = graphs.build_csr(n, s, d)
+        assert got == oracle.census(want_g), k
+        off, nb, fl = (x.cpu().numpy() for x in new)
+        assert np.array_equal(off, want_g.offsets)
+        assert np.array_equal(nb, want_g.nbrs)
+        assert np.array_equal(fl, want_g.flags)
+        census, dev, nnz = got, new, int(nb.size)
+    return census
+
+
+@pytest.mark.parametrize("n,density,recip,seed", [(12, 0.4, 0.3, 1), (60, 0.1, 0.2, 2), (300, 0.02, 0.5, 3)])
+def test_random_digraph_series(torch, n, density, recip, seed):
+    s, d = random_digraph(n, density, recip, seed)
+    _run_series(torch, n, s, d, [1, 5, 40, 200, 0, 7], seed)
+
+
+def test_rmat_with_hubs(torch):
+    # R-MAT scale 12: updates land on hub rows (long neighbour lists, many
+    # changed pairs per row)
+    src, dst = graphs.rmat_arcs(12, 8 << 12, seed=4)
+    _run_series(torch, 1 << 12, src, dst, [3000, 1, 500], 11)
+
+
+def test_from_empty_and_to_empty(torch):
+    n = 9
+    arcs = [(0, 1), (1, 2), (2, 0), (3, 4), (4, 3), (5, 6), (6, 7), (7, 5), (8, 0)]
+    s = np.array([a for a, _ in arcs], np.int32)
+    d = np.array([b for _, b in arcs], np.int32)
+    empty = graphs.build_csr(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    dev = triad.to_device(empty)
+    t = [torch.from_numpy(a).cuda() for a in (s, d, np.ones(s.size, np.uint8))]
+    got, new, changed = triad.census_update(n, 0, *dev, oracle.census(empty), *t)
+    full = graphs.build_csr(n, s, d)
+    assert got == oracle.census(full)
+    assert changed == 8  # 3-4 / 4-3 is one pair
+    t = [torch.from_numpy(a).cuda() for a in (s, d, np.zeros(s.size, np.uint8))]
+    got2, new2, _ = triad.census_update(n, full.nnz, *new, got, *t)
+    assert got2 == oracle.census(empty)
+    assert int(new2[1].numel()) == 0 and np.all(new2[0].cpu().numpy() == 0)
+
+
+def test_wrapped_003(torch):
+    # 003 above 2^64 before and after
+    n = 4801300
+    g = graphs.from_arcs(n, [(0, 1), (5, 6)])
+    dev = triad.to_device(g)
+    us, ud, ui = np.array([1, 5, 7], np.int32), np.array([0, 6, 9], np.int32), np.array([1, 0, 1], np.uint8)
+    t = [torch.from_numpy(a).cuda() for a in (us, ud, ui)]
+    got, new, _ = triad.census_update(n, g.nnz, *dev, oracle.census(g), *t, new_csr=False)
+    s, d = apply_updates(*g.arcs(), us, ud, ui)
+    assert new is None
+    assert got == oracle.census(graphs.build_csr(n, s, d))
+
+
+def test_update_errors(torch):
+    g = graphs.rmat(6, 4, seed=1)
+    dev = triad.to_device(g)
+    c = oracle.census(g)
+    for us, ud, ui, status in (([3], [3], [1], triad.ESELFLOOP), ([0], [g.n], [1], triad.ERANGE),
+                               ([0], [1], [2], triad.ERANGE)):
+        t = [torch.tensor(a, dtype=dt, device="cuda") for a, dt in ((us, torch.int32), (ud, torch.int32),
+                                                                   (ui, torch.uint8))]
+        with pytest.raises(triad.TriadError) as e:
+            triad.census_update(g.n, g.nnz, *dev, c, *t)
+        assert e.value.status == status
