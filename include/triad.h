@@ -158,6 +158,21 @@ int triad_census_device_noalloc(int64_t n, int64_t nnz, const int64_t *csr_offse
                                 const uint8_t *dir_flags, const triad_opts *opts, void *hip_stream,
                                 uint64_t *d_out, uint64_t *h_out);
 
+/* The 64-state labelled census (Sec. 3: the 64 states of a triad before they
+ * are condensed into 16 classes) of one graph given by DEVICE pointers, same
+ * arguments as triad_census_device. The vertices of a triple are named by id
+ * order, a < b < c, and its state is f_ab | f_ac << 2 | f_bc << 4 (f_xy the
+ * direction flag of y in row x: bit0 = x->y, bit1 = y->x, 0 = no arc). Output
+ * (d_out on the device and, if not NULL, h_out on the host): 65 x uint64, the
+ * count of triples in each state 0..63, then the high word of state 0 (no
+ * arc: C(n,3) minus the rest); TRIAD_OK_003_WRAPPED when that high word is not
+ * zero. Condensing state s into the class of the triad code s gives the
+ * census of triad_census_device. Options as there, except task_cycles,
+ * kernel_variant and waves_per_group (must be 0). */
+int triad_labelled_census_device(int64_t n, int64_t nnz, const int64_t *csr_offsets, const int32_t *csr_nbrs,
+                                 const uint8_t *dir_flags, const triad_opts *opts, void *hip_stream,
+                                 uint64_t *d_out, uint64_t *h_out);
+
 /* Host-side validation of the input contract (no device needed). level 0 =
  * cheap checks, 1 = also symmetry and mirrored flags. Returns TRIAD_OK or the
  * error status the census would return. */

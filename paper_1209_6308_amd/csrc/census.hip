@@ -389,6 +389,7 @@ struct CensusArgs {
   unsigned long long* gout;  // batched census: [graphs][16] accumulators
   const uint32_t* err;
   ClassSlices cls;           // nibble idx = fa | fb << 2 -> class; idx 0 -> 0 (not counted)
+  LabTables lab;             // labelled census: states of ids found in one list only
 };
 
 constexpr int PAD = 1024;   // readable entries past the end of the packed array
@@ -400,13 +401,25 @@ constexpr uint32_t LOP_S = 64, LOP_G = 128;
 // class counters, one per (class, lane). HH = true shares each counter between
 // lanes l and l+32, which the LDS serves in different halves of a wave64
 // access, halving the array.
-template <int W, bool HH>
+template <int W, bool HH, int NC = 16>
 struct WaveLds {
   static constexpr int COLS = HH ? 32 : 64;
+  static constexpr int NCLS = NC;
   uint32_t a[W + 1];
   uint32_t b[W + 1];
-  uint32_t hist[16 * COLS];  // [class][column]
+  uint32_t hist[NC * COLS];  // [class or state][column]
 };
+
+// Labelled census (64 states of a triple a < b < c by id order, Sec. 3): the
+// state of the triple of task (u, v) and a counted third vertex w, from the
+// flags fa = f_uw (0 if w is not in N(u)) and fb = f_vw: above v the triple
+// is (u, v, w) and its state f | fa << 2 | fb << 4 (f = f_uv); between u and
+// v it is (u, w, v), w not adjacent to u, and its state f << 2 | f_wv << 4,
+// f_wv the mirror of fb.
+__device__ __forceinline__ uint32_t mirror_flag(uint32_t f) { return ((f & 1u) << 1) | (f >> 1); }
+__device__ __forceinline__ uint32_t lab_state(bool above_v, uint32_t f, uint32_t fa, uint32_t fb) {
+  return above_v ? (f | fa << 2 | fb << 4) : (f << 2 | mirror_flag(fb) << 4);
+}
 
 // Merge-path split of the diagonal d of A (la) and B (lb) in global memory:
 // the number of A elements among the first d merged (A first on equal ids).
@@ -434,14 +447,34 @@ struct Batch {
   int64_t aoff, boff, tid;
   uint32_t la, lb, uf, vf, gid;
   int32_t dyad;
+  // labelled census: the dyadic triads of the task with the third vertex
+  // below u, between u and v, above v, less the common neighbours there
+  int32_t dlo, dmid, dhi;
 };
 
 // Adds the batch's dyadic terms n - d(u) - d(v) (Fig. 5 step 2.1.3; the
 // common-neighbour part is added by k_finalize) to counter 012 or 102 by the
 // u-v dyad: one wave reduction and one atomic per counter when the whole batch
 // belongs to one graph, per-lane atomics otherwise (batched census only).
-template <bool BAT>
+template <bool BAT, bool LAB>
 __device__ void add_dyads(const CensusArgs& g, int lane, const Batch& bt) {
+  if constexpr (LAB) {
+    // per range and u-v flag f: states f << 4 (w < u), f << 2 (u < w < v), f
+    const uint32_t f = bt.vf & 3u;
+#pragma unroll
+    for (uint32_t ff = 1; ff <= 3; ++ff) {
+      const bool mine = f == ff;  // lanes without a task, and later chunks, hold zeros
+      const uint64_t lo = wave_sum64(mine ? (uint64_t)(int64_t)bt.dlo : 0);
+      const uint64_t mid = wave_sum64(mine ? (uint64_t)(int64_t)bt.dmid : 0);
+      const uint64_t hi = wave_sum64(mine ? (uint64_t)(int64_t)bt.dhi : 0);
+      if (lane == 0) {
+        if (lo) atomicAdd(&g.acc[ff << 4], (unsigned long long)lo);
+        if (mid) atomicAdd(&g.acc[ff << 2], (unsigned long long)mid);
+        if (hi) atomicAdd(&g.acc[ff], (unsigned long long)hi);
+      }
+    }
+    return;
+  }
   const uint64_t dv = (uint64_t)(int64_t)bt.dyad;
   const bool mut = (bt.vf & 3u) == 3u;
   const uint32_t g0 = bcast32(bt.gid, 0);
@@ -459,7 +492,18 @@ __device__ void add_dyads(const CensusArgs& g, int lane, const Batch& bt) {
 
 // Claims the next batch: hub chunks first (phase 0), then whole tasks
 // (phase 1). Returns false when both queues are drained.
-template <bool BAT>
+// Labelled census: the dyadic terms of task (u, v) by range of w, less the
+// common neighbours in each range (added back from the triangle states at the
+// end): k = index of v in row u, su = ids of N(u) below u, sv = ids of N(v)
+// below u, dvm = ids of N(v) below v.
+__device__ __forceinline__ void lab_dyads(Batch& bt, int64_t n, int64_t u, int64_t v, int64_t du, int64_t k, int64_t su,
+                                          int64_t sv, int64_t dv, int64_t dvm) {
+  bt.dlo = (int32_t)(u - su - sv);
+  bt.dmid = (int32_t)((v - u - 1) - (k - su) - (dvm - sv - 1));
+  bt.dhi = (int32_t)((n - 1 - v) - (du - k - 1) - (dv - dvm));
+}
+
+template <bool BAT, bool LAB>
 __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt) {
   const int64_t hub_items = g.nhub ? g.hub_pre[g.nhub] : 0;
   for (;;) {
@@ -475,6 +519,7 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
     bt.cnt = (int)uni((uint32_t)min((int64_t)BATCH, limit - (int64_t)base));
     bt.la = bt.lb = bt.uf = bt.vf = bt.gid = 0;
     bt.dyad = 0;
+    bt.dlo = bt.dmid = bt.dhi = 0;
     bt.aoff = bt.boff = bt.tid = 0;
     if (lane < bt.cnt) {
       if (phase == 0) {
@@ -521,6 +566,12 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
           nn = g.vbase[bt.gid + 1] - g.vbase[bt.gid];
         }
         bt.dyad = c == 0 ? (int32_t)(nn - (int64_t)du - (int64_t)dv) : 0;
+        if constexpr (LAB) {
+          if (c == 0) {
+            const uint32_t vv = pv >> 2;
+            lab_dyads(bt, g.n, u, vv, du, (int64_t)(uint32_t)tk, su, min(g.tskip[bt.tid], dv), dv, g.ustart[vv]);
+          }
+        }
       } else {
         bt.tid = g.order ? g.order[base + lane] : (int64_t)base + lane;
         const uint64_t tk = g.tasks[bt.tid];
@@ -545,10 +596,14 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
             nn = g.vbase[bt.gid + 1] - g.vbase[bt.gid];
           }
           bt.dyad = (int32_t)(nn - (int64_t)du - (int64_t)dv);
+          if constexpr (LAB) {
+            const uint32_t vv = pv >> 2;
+            lab_dyads(bt, g.n, u, vv, du, (int64_t)(uint32_t)tk, g.ustart[u], sv, dv, g.ustart[vv]);
+          }
         }
       }
     }
-    add_dyads<BAT>(g, lane, bt);
+    add_dyads<BAT, LAB>(g, lane, bt);
     return true;
   }
 }
@@ -633,9 +688,10 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t* x, uint32_t n, uint
 // Per-lane two-pointer walk of the lane's merge-path range of one round:
 // one distinct w per step, classified in situ from its direction bits
 // (Fig. 5 steps 2.1.4-2.1.4.2, Sec. 6).
-template <int W, bool HH>
-__device__ __forceinline__ void merge_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
-                                                uint32_t vq, uint64_t slice, uint32_t col, int lane) {
+template <int W, bool HH, int NC>
+__device__ __forceinline__ void merge_round(WaveLds<W, HH, NC>& L, uint32_t na, uint32_t nb, uint32_t uq,
+                                                uint32_t vq, uint64_t slice, uint32_t fuv, uint32_t col, int lane) {
+  constexpr bool LAB = NC == 64;
   const uint32_t D = na + nb;
   const uint32_t d0 = (uint32_t)(((uint64_t)lane * D) >> 6), d1 = (uint32_t)(((uint64_t)(lane + 1) * D) >> 6);
   uint32_t lo = d0 > nb ? d0 - nb : 0, hi = d0 < na ? d0 : na;
@@ -664,9 +720,17 @@ __device__ __forceinline__ void merge_round(WaveLds<W, HH>& L, uint32_t na, uint
     // list that does not hold w, or of an uncounted w, taken as 0
     const uint32_t fa = __builtin_amdgcn_inverse_ballot_w64(mA) ? a & 3u : 0u;
     const uint32_t sb = __builtin_amdgcn_inverse_ballot_w64(mB) ? b : 0u;
-    const uint32_t sh = (((sb << 2) | fa) << 2) & 63u;  // the id bits of b shift out
-    const uint32_t cls = (uint32_t)(slice >> sh) & 15u;
-    atomicAdd(hcol + cls * WaveLds<W, HH>::COLS, 1u);
+    uint32_t cls;
+    if constexpr (LAB) {
+      // a counted w from N(u) lies above v; one from N(v) only may lie below it
+      const bool cnt = __builtin_amdgcn_inverse_ballot_w64(mA | mB);
+      const uint32_t st = lab_state(__builtin_amdgcn_inverse_ballot_w64(mA) | (eb > vq), fuv, fa, sb & 3u);
+      cls = cnt ? st : 0u;
+    } else {
+      const uint32_t sh = (((sb << 2) | fa) << 2) & 63u;  // the id bits of b shift out
+      cls = (uint32_t)(slice >> sh) & 15u;
+    }
+    atomicAdd(hcol + cls * WaveLds<W, HH, NC>::COLS, 1u);
     i += (uint32_t)ta;
     k += (uint32_t)tb;
     pos = i + k;
@@ -680,11 +744,12 @@ __device__ __forceinline__ void merge_round(WaveLds<W, HH>& L, uint32_t na, uint
 // found in its own list only, in 64-wide chunks, and the match of an S id
 // takes that one-list count back. Counter columns can therefore dip below
 // zero between flushes; flush_wave sums them as signed values.
-template <int W, bool HH>
-__device__ __forceinline__ void lopsided_round(WaveLds<W, HH>& L, uint32_t na, uint32_t nb, uint32_t uq,
-                                                   uint32_t vq, uint64_t slice, uint32_t ga, uint32_t gb, uint32_t col,
-                                                   int lane) {
-  constexpr uint32_t C = WaveLds<W, HH>::COLS;
+template <int W, bool HH, int NC>
+__device__ __forceinline__ void lopsided_round(WaveLds<W, HH, NC>& L, uint32_t na, uint32_t nb, uint32_t uq,
+                                                   uint32_t vq, uint64_t slice, uint32_t ga, uint32_t gb, uint32_t fuv,
+                                                   const LabTables& lt, uint32_t col, int lane) {
+  constexpr uint32_t C = WaveLds<W, HH, NC>::COLS;
+  constexpr bool LAB = NC == 64;
   const bool sA = na <= nb;  // the short window is N(u)'s
   const uint32_t* S = sA ? L.a : L.b;
   const uint32_t* G = sA ? L.b : L.a;
@@ -727,13 +792,33 @@ __device__ __forceinline__ void lopsided_round(WaveLds<W, HH>& L, uint32_t na, u
     const bool common = act & (key_of(gr) == kx);
     const uint32_t fs = x & 3u, fg = common ? gr & 3u : 0u;
     // canonical selection (Fig. 5 step 2.1.4) for the S id
-    const bool counted = act & (sA | common ? kx > vq : kx > uq);
-    const uint32_t idx = sA ? fs | fg << 2 : fg | fs << 2;
-    const uint32_t cls = counted ? (uint32_t)(slice >> (idx << 2)) & 15u : 0u;
+    const bool counted = act & ((sA | common) ? kx > vq : kx > uq);
+    uint32_t cls, gcls;
+    if constexpr (LAB) {
+      const uint32_t fa = sA ? fs : fg, fb = sA ? fg : fs;
+      cls = counted ? lab_state(kx > vq, fuv, fa, fb) : 0u;
+      // the G-only state the matched G id gets below
+      gcls = (common & (kx > thrG)) ? (sA ? lab_state(kx > vq, fuv, 0u, fg) : lab_state(true, fuv, fg, 0u)) : 0u;
+    } else {
+      const uint32_t idx = sA ? fs | fg << 2 : fg | fs << 2;
+      cls = counted ? (uint32_t)(slice >> (idx << 2)) & 15u : 0u;
+      gcls = (common & (kx > thrG)) ? (rowtbl >> (4u * fg)) & 15u : 0u;
+    }
     atomicAdd(hcol + cls * C, 1u);
     // the matched G id is counted below as found in G only: take that back
-    const uint32_t gcls = (common & (kx > thrG)) ? (rowtbl >> (4u * fg)) & 15u : 0u;
     if (common) atomicSub(hcol + gcls * C, 1u);
+  }
+  if constexpr (LAB) {
+    // ids of G as found in G only: N(v) only (sA) counts above u, its state
+    // depending on the side of v; N(u) only counts above v. Tables hold the
+    // state per flag in 8-bit fields (field 0 = uncounted).
+    const uint32_t thi = sA ? lt.gb_hi[fuv] : lt.ga_hi[fuv], tlo = sA ? lt.gb_lo[fuv] : 0u;
+    for (uint32_t e = (uint32_t)lane; e - (uint32_t)lane < ng; e += 64) {
+      const uint32_t y = G[e < ng ? e : 0];
+      const uint32_t off = (e < ng) & (y > thrG) ? y << 3 : 0u;
+      atomicAdd(hcol + __builtin_amdgcn_ubfe(y > vq ? thi : tlo, off, 6) * C, 1u);
+    }
+    return;
   }
   // ids of G, classified as found in G only, 64 per step. G is sorted: if
   // its last id is not above the threshold none is counted, if its first is
@@ -771,18 +856,18 @@ __device__ __forceinline__ void lopsided_round(WaveLds<W, HH>& L, uint32_t na, u
   }
 }
 
-template <int W, bool HH>
-__device__ void flush_wave(WaveLds<W, HH>& L, int lane, unsigned long long* acc) {
-  constexpr int C = WaveLds<W, HH>::COLS;
+template <int W, bool HH, int NC>
+__device__ void flush_wave(WaveLds<W, HH, NC>& L, int lane, unsigned long long* acc) {
+  constexpr int C = WaveLds<W, HH, NC>::COLS;
   wave_lds_sync();
-  for (int c = 1; c < 16; ++c) {
+  for (int c = 1; c < NC; ++c) {
     // columns are signed: a lopsided round may take a count back from a column
     // other than the one that received it
     const uint64_t x = lane < C ? (uint64_t)(int64_t)(int32_t)L.hist[c * C + lane] : 0u;
     const uint64_t sum = wave_sum64(x);
     if (lane == 0 && sum) atomicAdd(&acc[c], (unsigned long long)sum);
   }
-  for (int c = 0; c < 16; ++c)
+  for (int c = 0; c < NC; ++c)
     if (lane < C) L.hist[c * C + lane] = 0;
   wave_lds_sync();
 }
@@ -795,15 +880,16 @@ __device__ void flush_wave(WaveLds<W, HH>& L, int lane, unsigned long long* acc)
 // (a wavefront flushes its LDS counters when it moves to another graph).
 template <int WAVES, int W, bool HH, int MODE, int MINW>
 __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
-  constexpr bool CYC = MODE == 1, BAT = MODE == 2;
-  __shared__ WaveLds<W, HH> lds[WAVES];
-  constexpr int C = WaveLds<W, HH>::COLS;
+  constexpr bool CYC = MODE == 1, BAT = MODE == 2, LAB = MODE == 3;
+  constexpr int NC = LAB ? 64 : 16;
+  __shared__ WaveLds<W, HH, NC> lds[WAVES];
+  constexpr int C = WaveLds<W, HH, NC>::COLS;
   if (*g.err) return;
   const int lane = threadIdx.x & 63;
-  WaveLds<W, HH>& L = lds[threadIdx.x >> 6];
+  WaveLds<W, HH, NC>& L = lds[threadIdx.x >> 6];
   const int64_t wave_id = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
   if (g.wave_span && lane == 0) g.wave_span[2 * wave_id] = __builtin_amdgcn_s_memrealtime();
-  for (int c = 0; c < 16; ++c)
+  for (int c = 0; c < NC; ++c)
     if (lane < C) L.hist[c * C + lane] = 0;
   wave_lds_sync();
   const uint32_t col = (uint32_t)(lane & (C - 1));
@@ -875,7 +961,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
         // batch exhausted: claim the next one (the current item is already in
         // scalars, so bt can be overwritten; this latency is not hidden)
         for (;;) {
-          more = uni(fetch_batch<BAT>(g, lane, phase, bt));
+          more = uni(fetch_batch<BAT, LAB>(g, lane, phase, bt));
           if (!more) break;
           int k0 = 0;
           while (k0 < bt.cnt && bcast32(bt.la, k0) + bcast32(bt.lb, k0) == 0) ++k0;
@@ -905,10 +991,10 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
       wg = cur.gid;
     }
     if (min(na, nb) <= LOP_S && max(na, nb) >= LOP_G)
-      lopsided_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice,
-                                          g.cls.ga[cur.f], g.cls.gb[cur.f], col, lane);
+      lopsided_round<W, HH, NC>(L, na, nb, cur.uq, cur.vq, cur.slice, g.cls.ga[cur.f], g.cls.gb[cur.f], cur.f, g.lab,
+                                col, lane);
     else
-      merge_round<W, HH>(L, na, nb, cur.uq, cur.vq, cur.slice, col, lane);
+      merge_round<W, HH, NC>(L, na, nb, cur.uq, cur.vq, cur.slice, cur.f, col, lane);
     steps += (na + nb) / (HH ? 16 : 32) + 4;
     if (item_done) {
       if constexpr (CYC) {
@@ -960,6 +1046,34 @@ __global__ void k_finalize(const unsigned long long* __restrict__ acc, uint64_t 
   }
   out[0] = clo - s;
   out[16] = chi - (clo < s ? 1u : 0u);
+}
+
+// Labelled census: each triangle {a < b < c} is a common neighbour of three
+// of its edges' tasks, so the dyadic terms of those tasks (which subtracted
+// it) get it back: the task (b, c) below u (state f_bc << 4), the task (a, c)
+// between u and v (state f_ac << 2), the task (a, b) above v (state f_ab).
+// State 0 (no arc) = C(n,3) minus the rest, in two 64-bit words (out[64] is
+// the high word).
+__global__ void k_finalize_lab(const unsigned long long* __restrict__ acc, uint64_t clo, uint64_t chi,
+                               uint64_t* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t c[64];
+  for (int k = 0; k < 64; ++k) c[k] = acc[k];
+  for (uint32_t st = 1; st < 64; ++st) {
+    const uint32_t fab = st & 3u, fac = (st >> 2) & 3u, fbc = st >> 4;
+    if (fab && fac && fbc) {
+      c[fbc << 4] += acc[st];
+      c[fac << 2] += acc[st];
+      c[fab] += acc[st];
+    }
+  }
+  uint64_t s = 0;
+  for (int k = 1; k < 64; ++k) {
+    out[k] = c[k];
+    s += c[k];
+  }
+  out[0] = clo - s;
+  out[64] = chi - (clo < s ? 1u : 0u);
 }
 
 __global__ void k_fill_u64(uint64_t* p, int64_t m, uint64_t v) {
@@ -1052,6 +1166,24 @@ static hipError_t launch_census(int waves, int variant, const CensusArgs& a, int
   }
 }
 
+// The labelled census (64 counters per column: 8 KB of LDS per wavefront)
+// runs one launch shape: 448-entry windows, two wavefronts per workgroup.
+constexpr int LAB_WAVES = 2;
+static hipError_t launch_lab(const CensusArgs& a, int groups, hipStream_t s) {
+  k_census<LAB_WAVES, 448, true, 3, 3><<<groups, LAB_WAVES * 64, 0, s>>>(a);
+  return hipGetLastError();
+}
+static int lab_groups(int requested) {
+  if (requested > 0) return requested;
+  DeviceInfo di;
+  if (device_info(&di) != TRIAD_OK) return 1024;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<LAB_WAVES, 448, true, 3, 3>, LAB_WAVES * 64, 0) !=
+          hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return di.cus * per_cu;
+}
+
 static int census_groups(int waves, int variant, int cyc, int requested) {
   if (requested > 0) return requested;
   DeviceInfo di;
@@ -1121,11 +1253,16 @@ static size_t census_scratch_bound(int64_t n, int64_t nnz) {
   return b;
 }
 
+// The census of one device-resident graph. labelled: the 64-state census
+// (65 output words) instead of the 16 classes (17 words).
 int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
                   const triad_opts* opts, hipStream_t s, uint64_t* d_out, uint64_t* h_out, void* arena = nullptr,
-                  size_t arena_bytes = 0) {
+                  size_t arena_bytes = 0, bool labelled = false) {
   triad_opts o{};
   if (opts) o = *opts;
+  const int NC = labelled ? 64 : 16;  // census counters
+  if (labelled && (o.task_cycles || o.kernel_variant || o.waves_per_group))
+    return fail(TRIAD_EINVAL, "the labelled census takes no cycle recording and no kernel variant");
   if (n < 0 || n >= ((int64_t)1 << 30)) return fail(TRIAD_EINVAL, "n must be in [0, 2^30)");
   if (nnz < 0 || nnz >= ((int64_t)1 << 40)) return fail(TRIAD_EINVAL, "nnz must be in [0, 2^40)");
   if (!off || !d_out || (nnz > 0 && (!nbr || !flg))) return fail(TRIAD_EINVAL, "NULL pointer argument");
@@ -1154,11 +1291,11 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   if (o.timing) HIPCHK(ev.init());
   Scratch scratch = arena ? Scratch(s, arena, arena_bytes) : Scratch(s);
   uint32_t* err = nullptr;
-  unsigned long long* acc = nullptr;  // [16] census accumulators + [2] queue counters + [1] hub count
+  unsigned long long* acc = nullptr;  // NC census counters, 2 queue counters, hub tasks, long rows
   ALLOC(err, 1);
-  ALLOC(acc, 20);  // 16 classes, 2 queue counters, hub tasks, long rows
+  ALLOC(acc, NC + 4);
   k_fill_u32<<<1, 64, 0, s>>>(err, 1, 0);
-  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)acc, 20, 0);
+  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)acc, NC + 4, 0);
   uint64_t clo, chi;
   choose3(n, &clo, &chi);
   ev.rec(0, s);
@@ -1210,7 +1347,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     ALLOC(hub_pre, hub_cap + 1);
     uint64_t* long_segs = nullptr;
     ALLOC(long_segs, emit_seg_cap(n, ntasks));
-    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, 1, hub_thr, long_segs, acc + 19, err};
+    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, 1, hub_thr, long_segs, acc + NC + 3, err};
     launch_emit(e, s);
     // A schedule reorders the last batches of the queue: in place, or, with
     // per-task cycle recording, through a queue-position -> task index map
@@ -1224,11 +1361,11 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     }
     if (hub_thr >= 0)
       k_hub_list<<<grid_for(ntasks, HUB_TILE, 32768), 256, 0, s>>>(tasks, ntasks, off, packed, chunk, hub_task, hub_nch,
-                                                                   acc + 18, err);
+                                                                   acc + NC + 2, err);
     HIPCHK(hipGetLastError());
     if (hub_thr >= 0) {
       unsigned long long hc = 0;
-      HIPCHK(hipMemcpyAsync(&hc, acc + 18, sizeof(hc), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&hc, acc + NC + 2, sizeof(hc), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       nhub = (int64_t)hc;
       if (nhub > 0) {
@@ -1253,21 +1390,32 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     a.hub_pre = hub_pre;
     a.nhub = nhub;
     a.chunk = chunk;
-    a.qctr = acc + 16;
+    a.qctr = acc + NC;
     a.acc = acc;
     a.cycles = o.task_cycles;
     a.wave_span = o.wave_span;
     a.err = err;
     a.cls = class_slices();
-    groups = census_groups(waves, variant, a.cycles != nullptr ? 1 : 0, o.grid_groups);
-    HIPCHK(launch_census(waves, variant, a, groups, s));
+    a.lab = lab_tables();
+    if (labelled) {
+      groups = lab_groups(o.grid_groups);
+      HIPCHK(launch_lab(a, groups, s));
+    } else {
+      groups = census_groups(waves, variant, a.cycles != nullptr ? 1 : 0, o.grid_groups);
+      HIPCHK(launch_census(waves, variant, a, groups, s));
+    }
     HIPCHK(hipGetLastError());
   }
   ev.rec(3, s);
-  k_finalize<<<1, 64, 0, s>>>(acc, clo, chi, d_out);
+  if (labelled)
+    k_finalize_lab<<<1, 64, 0, s>>>(acc, clo, chi, d_out);
+  else
+    k_finalize<<<1, 64, 0, s>>>(acc, clo, chi, d_out);
   HIPCHK(hipGetLastError());
   ev.rec(4, s);
-  if (h_out) HIPCHK(hipMemcpyAsync(h_out, d_out, 17 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  if (h_out) HIPCHK(hipMemcpyAsync(h_out, d_out, (NC + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  uint64_t hi0 = 0;  // high word of the null count
+  HIPCHK(hipMemcpyAsync(&hi0, d_out + NC, sizeof hi0, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&errh, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (errh) return fail(status_from_bits(errh), "input validation failed on the device");
@@ -1279,9 +1427,9 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     o.timing->tasks = ntasks;
     o.timing->hub_tasks = nhub;
     o.timing->items = ntasks;
-    o.timing->waves = (int64_t)groups * waves;
+    o.timing->waves = (int64_t)groups * (labelled ? LAB_WAVES : waves);
   }
-  return chi ? TRIAD_OK_003_WRAPPED : TRIAD_OK;
+  return hi0 ? TRIAD_OK_003_WRAPPED : TRIAD_OK;
 }
 
 
@@ -1606,6 +1754,11 @@ int triad_census_device_noalloc(int64_t n, int64_t nnz, const int64_t* off, cons
 int triad_census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
                         const triad_opts* opts, void* stream, uint64_t* d_out, uint64_t* h_out) {
   return census_device(n, nnz, off, nbr, flg, opts, (hipStream_t)stream, d_out, h_out);
+}
+
+int triad_labelled_census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
+                                 const triad_opts* opts, void* stream, uint64_t* d_out, uint64_t* h_out) {
+  return census_device(n, nnz, off, nbr, flg, opts, (hipStream_t)stream, d_out, h_out, nullptr, 0, true);
 }
 
 int triad_census_ex(int64_t n, const int64_t* off, const int32_t* nbr, const uint8_t* flg, const triad_opts* opts,

@@ -90,6 +90,23 @@ ClassSlices class_slices() {
   return cs;
 }
 
+LabTables lab_tables() {
+  LabTables t{};
+  for (unsigned f = 0; f < 4; ++f) {
+    uint32_t ahi = 0, bhi = 0, blo = 0;
+    for (unsigned g = 1; g < 4; ++g) {
+      const unsigned gm = ((g & 1u) << 1) | (g >> 1);
+      ahi |= (f | g << 2) << (8 * g);
+      bhi |= (f | g << 4) << (8 * g);
+      blo |= (f << 2 | gm << 4) << (8 * g);
+    }
+    t.ga_hi[f] = ahi;
+    t.gb_hi[f] = bhi;
+    t.gb_lo[f] = blo;
+  }
+  return t;
+}
+
 void choose3(int64_t n, uint64_t* lo, uint64_t* hi) {
   unsigned __int128 r = 0;
   if (n >= 3) r = (unsigned __int128)(uint64_t)n * (uint64_t)(n - 1) * (uint64_t)(n - 2) / 6;

@@ -39,6 +39,15 @@ struct ClassSlices {
   uint32_t ga[4], gb[4];
 };
 ClassSlices class_slices();
+
+// Labelled census (64 states of a triple a < b < c): per f_uv, the state of a
+// third vertex w found in one list only, by its flag g, in 8-bit field g
+// (field 0 = 0, not counted): N(u) only above v (f | g << 2), N(v) only above
+// v (f | g << 4), N(v) only between u and v (f << 2 | mirror(g) << 4).
+struct LabTables {
+  uint32_t ga_hi[4], gb_hi[4], gb_lo[4];
+};
+LabTables lab_tables();
 int classify_code(unsigned code);  // 0..15, standard order
 
 // C(n,3) as (lo, hi) 64-bit words.

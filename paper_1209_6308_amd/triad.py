@@ -33,7 +33,8 @@ MLP_IN, MLP_HIDDEN = 6, 32
 MLP_PARAMS = MLP_HIDDEN * MLP_IN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN + 1
 
 EXPORTS = [
-    "triad_census", "triad_census_ex", "triad_census_device", "triad_census_device_noalloc", "triad_validate_host",
+    "triad_census", "triad_census_ex", "triad_census_device", "triad_census_device_noalloc",
+    "triad_labelled_census_device", "triad_validate_host",
     "triad_batch_plan_create", "triad_batch_plan_launch", "triad_batch_plan_status",
     "triad_batch_plan_destroy", "triad_census_batch", "triad_batch_autotune",
     "triad_csr_from_arcs", "triad_census_update", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
@@ -82,6 +83,7 @@ def lib():
             "triad_census_ex": [i64, vp, vp, vp, po, vp, vp],
             "triad_census_device": [i64, i64, vp, vp, vp, po, vp, vp, vp],
             "triad_census_device_noalloc": [i64, i64, vp, vp, vp, po, vp, vp, vp],
+            "triad_labelled_census_device": [i64, i64, vp, vp, vp, po, vp, vp, vp],
             "triad_validate_host": [i64, vp, vp, vp, i32],
             "triad_batch_plan_create": [i32, i64, i64, vp, vp, vp, vp, vp, po, vp, ctypes.POINTER(vp)],
             "triad_batch_plan_launch": [vp, vp],
@@ -208,6 +210,22 @@ def triad_census_device_noalloc(n, nnz, d_off, d_nbr, d_flg, d_out, stream=None,
     st = _check(lib().triad_census_device_noalloc(n, nnz, _tp(d_off), _tp(d_nbr), _tp(d_flg), ctypes.byref(o),
                                                   _stream(stream), _tp(d_out), _p(h)))
     return _result(h, h[16]), st
+
+
+def labelled_census_device(n, nnz, d_off, d_nbr, d_flg, stream=None, d_out=None, **kw):
+    """64-state labelled census from torch device tensors: returns (64 Python
+    ints, state 0 including its high word; status; timing dict)."""
+    import torch
+    if d_out is None:
+        d_out = torch.empty(65, dtype=torch.int64, device=d_off.device)
+    h = np.zeros(65, dtype=np.uint64)
+    tm = Timing()
+    o = make_opts(timing=tm, **kw)
+    st = _check(lib().triad_labelled_census_device(n, nnz, _tp(d_off), _tp(d_nbr), _tp(d_flg), ctypes.byref(o),
+                                                   _stream(stream), _tp(d_out), _p(h)))
+    res = [int(x) for x in h[:64]]
+    res[0] += int(h[64]) << 64
+    return res, st, tm.as_dict()
 
 
 def to_device(g, device="cuda"):
