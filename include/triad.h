@@ -257,6 +257,21 @@ int triad_census_update(int64_t n, int64_t nnz, const int64_t *d_offsets, const 
                         int64_t *d_offsets_new, int32_t *d_nbrs_new, uint8_t *d_flags_new, int64_t *nnz_new,
                         int64_t *changed_pairs, void *hip_stream);
 
+/* ------------------------------------------------- significance profile
+ * Triad significance profile of a graph against a null-model ensemble (for
+ * example degree-preserving randomisations of it, censused in one batch):
+ * d_ensemble (DEVICE, G x 16 uint64, graph-major: the output of a batched
+ * census) and real (HOST, 16 uint64: the graph's census; 003 below 2^64) give
+ * per type t the z-score z_out[t] = (real[t] - mean_t) / sd_t (HOST; mean and
+ * sample standard deviation of the ensemble, divisor G - 1; 0 where the
+ * ensemble's counts do not vary), and sp_out (HOST) the profile: the z-scores
+ * of the 13 connected types (021D ... 300) scaled to unit length, 0 for 003,
+ * 012, 102 (all 0 if every connected z-score is 0). Double precision. G >= 2;
+ * each type's counts must lie within 2^63 of the first graph's. Errors:
+ * TRIAD_EINVAL, TRIAD_ENOMEM, TRIAD_EDEVICE. Waits for its work on hip_stream. */
+int triad_significance_profile(int32_t G, const uint64_t *d_ensemble, const uint64_t real[16], double z_out[16],
+                               double sp_out[16], void *hip_stream);
+
 /* ------------------------------------------------------- learned schedule
  * Cost model: an FP32 multilayer perceptron 6 -> 32 -> 32 -> 1 with ReLU
  * hidden layers. Parameters, packed in this order: W1[32][6], b1[32],

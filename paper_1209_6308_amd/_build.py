@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_SOURCES = ["census.hip", "costmodel.hip", "csr_build.hip", "update.hip", "host.cpp"]
+HIP_SOURCES = ["census.hip", "costmodel.hip", "csr_build.hip", "update.hip", "profile.hip", "host.cpp"]
 
 
 def gen_lib_path():

@@ -501,6 +501,24 @@ int64_t tg_swap(int64_t narcs, int32_t* src, int32_t* dst, int64_t attempts, uin
   return acc;
 }
 
+// K degree-preserving randomisations of one arc list (copy k from the seed
+// stream (seed, k)), copy k written to out_src/out_dst[k * narcs ...].
+int64_t tg_swap_ensemble(int64_t narcs, const int32_t* src, const int32_t* dst, int32_t K, int64_t attempts,
+                         uint64_t seed, int32_t* out_src, int32_t* out_dst, int nthreads) {
+  int64_t acc = 0;
+#pragma omp parallel for num_threads(std::max(1, nthreads)) schedule(dynamic, 1) reduction(+ : acc)
+  for (int32_t k = 0; k < K; ++k) {
+    std::vector<uint32_t> s(narcs), d(narcs);
+    for (int64_t i = 0; i < narcs; ++i) { s[i] = (uint32_t)src[i]; d[i] = (uint32_t)dst[i]; }
+    acc += swap_arcs(s, d, attempts, mix64(seed * 0x9e3779b97f4a7c15ull + (uint64_t)k + 1));
+    for (int64_t i = 0; i < narcs; ++i) {
+      out_src[(int64_t)k * narcs + i] = (int32_t)s[i];
+      out_dst[(int64_t)k * narcs + i] = (int32_t)d[i];
+    }
+  }
+  return acc;
+}
+
 void* tg_csr_build(int64_t n, int64_t narcs, const int32_t* src, const int32_t* dst, double recip_p,
                    uint64_t recip_seed, int nthreads) {
   return build_csr(n, narcs, src, dst, recip_p, recip_seed, nthreads);

@@ -46,6 +46,8 @@ def lib():
         L.tg_erdos_renyi.restype = i64
         L.tg_swap.argtypes = [i64, vp, vp, i64, u64]
         L.tg_swap.restype = i64
+        L.tg_swap_ensemble.argtypes = [i64, vp, vp, ctypes.c_int32, i64, u64, vp, vp, i32]
+        L.tg_swap_ensemble.restype = i64
         L.tg_csr_build.argtypes = [i64, i64, vp, vp, dbl, u64, i32]
         L.tg_csr_build.restype = vp
         L.tg_csr_nnz.argtypes = [vp]
@@ -282,3 +284,38 @@ def null_ensemble(G: int = 4096, seed: int = 1, nmin: int = 64, nmax: int = 8192
     finally:
         L.tg_batch_free(h)
     return BatchCSR(G, vb, off, nb, fl, pr)
+
+
+def concat_csrs(members, params=None) -> BatchCSR:
+    """One batch (graph-local ids, global entry offsets) from a list of CSRs."""
+    vb = [0]
+    offs, nbs, fls = [np.zeros(1, np.int64)], [], []
+    e0 = 0
+    for g in members:
+        vb.append(vb[-1] + g.n)
+        offs.append(g.offsets[1:] + e0)
+        nbs.append(g.nbrs)
+        fls.append(g.flag_array())
+        e0 += g.nnz
+    f = np.concatenate(fls) if fls else np.zeros(0, np.uint8)
+    j = np.arange(f.size)
+    packed = np.zeros((f.size + 3) // 4, np.uint8)
+    np.bitwise_or.at(packed, j >> 2, (f << (2 * (j & 3))).astype(np.uint8))
+    return BatchCSR(len(members), np.array(vb, np.int64), np.concatenate(offs).astype(np.int64),
+                    np.concatenate(nbs).astype(np.int32) if nbs else np.zeros(0, np.int32), packed,
+                    params if params is not None else np.zeros((len(members), 6)))
+
+
+def randomised_ensemble(g: CSR, K: int, seed: int = 1, swap_factor: float = 10.0) -> BatchCSR:
+    """K degree-preserving randomisations of g (double-edge swaps within
+    asymmetric arcs and within mutual dyads, swap_factor x arcs attempts each;
+    in-, out- and mutual degrees kept) as one batch: the null-model ensemble of
+    a triad significance profile."""
+    src, dst = g.arcs()
+    m = src.size
+    out_s = np.empty(K * m, dtype=np.int32)
+    out_d = np.empty(K * m, dtype=np.int32)
+    lib().tg_swap_ensemble(m, _p(src), _p(dst), K, int(swap_factor * m), seed, _p(out_s), _p(out_d), nthreads())
+    members = [build_csr(g.n, out_s[k * m:(k + 1) * m], out_d[k * m:(k + 1) * m]) for k in range(K)]
+    return concat_csrs(members)
+

@@ -37,7 +37,7 @@ EXPORTS = [
     "triad_labelled_census_device", "triad_validate_host",
     "triad_batch_plan_create", "triad_batch_plan_launch", "triad_batch_plan_status",
     "triad_batch_plan_destroy", "triad_census_batch", "triad_batch_autotune",
-    "triad_csr_from_arcs", "triad_census_update", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
+    "triad_csr_from_arcs", "triad_census_update", "triad_significance_profile", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
     "triad_mlp_train", "triad_last_error", "triad_version",
 ]
 
@@ -95,6 +95,7 @@ def lib():
                                     ctypes.POINTER(ctypes.c_float)],
             "triad_census_update": [i64, i64, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.POINTER(i64), ctypes.POINTER(i64), vp],
+            "triad_significance_profile": [i32, vp, vp, vp, vp, vp],
             "triad_task_features": [i64, i64, vp, vp, vp, vp, ctypes.POINTER(i64)],
             "triad_mlp_forward": [vp, vp, i64, vp, vp],
             "triad_mlp_loss_grad": [vp, vp, vp, i64, vp, vp, vp],
@@ -285,6 +286,18 @@ def census_update(n, nnz, d_off, d_nbr, d_flg, census, d_src, d_dst, d_ins, new_
         m = int(nn.value)
         out = (out[0], out[1][:m], out[2][:(m + 3) // 4])
     return _result(cout, cout[16]), out, int(chg.value)
+
+
+def significance_profile(d_ensemble, real, stream=None):
+    """z-scores and significance profile of the census `real` (16 ints) against
+    the batched censuses `d_ensemble` (device tensor [G, 16] of 64-bit counts).
+    Returns (z[16], sp[16]) as lists of floats."""
+    G = int(d_ensemble.shape[0])
+    r = np.array([int(x) & ((1 << 64) - 1) for x in real], dtype=np.uint64)
+    z = np.zeros(16, dtype=np.float64)
+    sp = np.zeros(16, dtype=np.float64)
+    _check(lib().triad_significance_profile(G, _tp(d_ensemble), _p(r), _p(z), _p(sp), _stream(stream)))
+    return z.tolist(), sp.tolist()
 
 
 # ------------------------------------------------------------------ batches

@@ -123,3 +123,28 @@ def test_null_ensemble_small():
         assert kind == (g & 1)
     C = graphs.null_ensemble(G=16, seed=3, nmin=64, nmax=300, dmin=4, dmax=12)
     assert C.content_hash() == B.content_hash()
+
+
+def test_randomised_ensemble_keeps_degrees():
+    g = graphs.rmat(9, 8, seed=4, recip_p=0.3)
+    B = graphs.randomised_ensemble(g, 6, seed=2)
+    assert B.G == 6 and np.array_equal(np.diff(B.vbase), np.full(6, g.n))
+
+    def degs(h):
+        f = h.flag_array()
+        rows = np.repeat(np.arange(h.n), np.diff(h.offsets))
+        out = np.bincount(rows[(f & 1) != 0], minlength=h.n)
+        inn = np.bincount(rows[(f & 2) != 0], minlength=h.n)
+        mut = np.bincount(rows[f == 3], minlength=h.n)
+        return out, inn, mut
+
+    want = degs(g)
+    changed = 0
+    for k in range(B.G):
+        m = B.graph(k)
+        for a, b in zip(degs(m), want):
+            assert np.array_equal(a, b)
+        changed += int(not np.array_equal(m.nbrs, g.nbrs))
+    assert changed == B.G  # every copy was rewired
+    again = graphs.randomised_ensemble(g, 6, seed=2)
+    assert again.content_hash() == B.content_hash()
