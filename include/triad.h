@@ -116,6 +116,9 @@ typedef struct triad_opts {
                               mean of the last 32,768 by tail_share / 10,000 of one
                               wavefront's share of the whole census; 0 = default
                               (30, i.e. 0.3%), < 0 = always */
+  int32_t short_tasks;     /* batched census: 0 = tasks whose two merged lists are short
+                              run several to a round (default), < 0 = every task through
+                              the per-task merge rounds */
 } triad_opts;
 
 /* Census of one graph given by HOST pointers (copied to the device; the call

@@ -364,6 +364,53 @@ static void launch_emit(const EmitArgs& e, hipStream_t s) {
   k_emit_long<<<16384, 256, 0, s>>>(e);
 }
 
+// Row of entry j: the last x in [lo, hi) with off[x] <= j, given off[lo] <= j
+// < off[hi] (an empty row is never the answer, since the row after it starts
+// at the same offset).
+__device__ __forceinline__ int64_t row_search(const int64_t* __restrict__ off, int64_t lo, int64_t hi, int64_t j) {
+  while (hi - lo > 1) {
+    const int64_t m = (lo + hi) >> 1;
+    if (off[m] <= j) lo = m; else hi = m;
+  }
+  return lo;
+}
+
+// Entry kernels take tiles of ETILE entries: two threads find the rows of the
+// tile's first and last entry over all offsets, and every entry then searches
+// only between those two rows.
+constexpr int ETILE = 4096;
+__device__ __forceinline__ void tile_rows(const int64_t* __restrict__ off, int64_t n, int64_t t0, int64_t t1,
+                                          int64_t* rr) {
+  __syncthreads();
+  if (threadIdx.x < 2) rr[threadIdx.x] = row_search(off, 0, n, threadIdx.x == 0 ? t0 : t1 - 1);
+  __syncthreads();
+}
+
+// Task list from the CSR entries, one thread per entry: entry j of row u with
+// an id above u is task tpre[u] + (j - off[u] - ustart[u]) (CSR order), with
+// its count of N(v) ids below u and its hub flag (emit_task). Every task is
+// as cheap as the next, whatever the lengths of the rows.
+__global__ void __launch_bounds__(256) k_emit_entries(EmitArgs e, int64_t nnz) {
+  __shared__ int64_t rr[2];
+  if (*e.err) return;
+  for (int64_t t0 = (int64_t)blockIdx.x * ETILE; t0 < nnz; t0 += (int64_t)gridDim.x * ETILE) {
+    const int64_t t1 = min(t0 + (int64_t)ETILE, nnz);
+    tile_rows(e.off, e.n, t0, t1, rr);
+    const int64_t r0 = rr[0], r1 = rr[1];
+    for (int64_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
+      const int64_t u = row_search(e.off, r0, r1 + 1, j);
+      const int64_t b = e.off[u];
+      const uint32_t k = (uint32_t)(j - b), su = e.ustart[u];
+      if (k >= su) emit_task(e, true, u, b, e.off[u + 1] - b, k, e.tpre[u] + (k - su));
+    }
+  }
+}
+
+static void launch_emit_entries(const EmitArgs& e, int64_t nnz, hipStream_t s) {
+  const int64_t tiles = (nnz + ETILE - 1) / ETILE;
+  k_emit_entries<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, 65536)), 256, 0, s>>>(e, nnz);
+}
+
 // ------------------------------------------------------------ the census
 
 struct CensusArgs {
@@ -375,6 +422,7 @@ struct CensusArgs {
   const uint64_t* tasks;   // the task queue
   const uint64_t* htasks;  // the task words the hub list indexes
   const int64_t* order;    // optional: queue position -> index into tasks
+  const int64_t* ntasks_dev;  // batched census: queue length read on the device
   int64_t ntasks;
   const uint64_t* hub_task;
   const int64_t* hub_pre;  // [nhub+1] exclusive prefix of chunk counts
@@ -508,7 +556,10 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
   const int64_t hub_items = g.nhub ? g.hub_pre[g.nhub] : 0;
   for (;;) {
     const int q = phase == 0 ? 0 : 1;
-    const int64_t limit = phase == 0 ? hub_items : g.ntasks;
+    int64_t limit = phase == 0 ? hub_items : g.ntasks;
+    if constexpr (BAT) {
+      if (phase == 1 && g.ntasks_dev) limit = *g.ntasks_dev;
+    }
     uint64_t base = 0;
     if (lane == 0) base = atomicAdd(&g.qctr[q], (unsigned long long)BATCH);
     base = bcast64(base, 0);
@@ -815,7 +866,7 @@ __device__ __forceinline__ void lopsided_round(WaveLds<W, HH, NC>& L, uint32_t n
     const uint32_t thi = sA ? lt.gb_hi[fuv] : lt.ga_hi[fuv], tlo = sA ? lt.gb_lo[fuv] : 0u;
     for (uint32_t e = (uint32_t)lane; e - (uint32_t)lane < ng; e += 64) {
       const uint32_t y = G[e < ng ? e : 0];
-      const uint32_t off = (e < ng) & (y > thrG) ? y << 3 : 0u;
+      const uint32_t off = ((e < ng) & (y > thrG)) ? y << 3 : 0u;
       atomicAdd(hcol + __builtin_amdgcn_ubfe(y > vq ? thi : tlo, off, 6) * C, 1u);
     }
     return;
@@ -851,7 +902,7 @@ __device__ __forceinline__ void lopsided_round(WaveLds<W, HH, NC>& L, uint32_t n
   }
   if (nfull < ng) {
     const uint32_t y = G[e];
-    const uint32_t off = (e < ng) & (y > thrG) ? y << 2 : 0u;
+    const uint32_t off = ((e < ng) & (y > thrG)) ? y << 2 : 0u;
     atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, off, 4) * C, 1u);
   }
 }
@@ -1019,6 +1070,257 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   if (BAT) tgt = wg != 0xFFFFFFFFu ? g.gout + 16 * (uint64_t)wg : nullptr;
   if (tgt) flush_wave(L, lane, tgt);
   if (lane == 0 && g.wave_span) g.wave_span[2 * wave_id + 1] = __builtin_amdgcn_s_memrealtime();
+}
+
+// ------------------------------------------------- short tasks, grouped
+// A task whose two merged lists (N(u) above u, N(v) from u) are short costs
+// little merging but a whole round of the item path. Such tasks run GT to a
+// round instead: the wavefront's two LDS windows are cut into GT slots of
+// GROUP_W / GT entries, one per task and list (the last entry of a slot holds
+// the sentinel), and each task gets 64 / GT lanes, each walking its merge-path
+// share of that task's merge (Fig. 8) and classifying every w in situ exactly
+// as the item path does. A wavefront claims GROUP_CLAIM consecutive tasks (CSR
+// order) at a time and takes them 64 at a time: every task is sized, the ones
+// whose longer list fits a slot for GT = 8, 4, 2 or 1 are sorted by that fit
+// (bin 0..3) into an LDS list and run GT per round; bin 4 (longer, or split)
+// is appended to a list the item path takes afterwards.
+constexpr int GROUP_W = 448;
+constexpr int GROUP_WAVES = 2;
+constexpr int GROUP_CLAIM = 1024;  // tasks per claim: claims of a shared counter must stay rare
+__host__ __device__ constexpr int group_tasks(int bin) { return 8 >> bin; }  // tasks per round of bins 0..3
+
+struct GroupTask {  // one task of a round
+  uint32_t aoff, boff;  // first entries of the two lists (entry indices < 2^32)
+  uint32_t lens;        // la | lb << 16
+  uint32_t uq, vq;      // u << 2 | 3 and v << 2 | f_uv
+  uint32_t gid;         // graph of the task (batched census)
+};
+
+struct GroupArgs {
+  const int64_t* off;
+  const uint32_t* packed;
+  const uint32_t* ustart;
+  const uint32_t* tskip;
+  const uint64_t* tasks;
+  int64_t ntasks;
+  const uint32_t* grow;   // batched: graph of each row (else NULL)
+  const int64_t* vbase;   // batched: first row of each graph
+  int64_t n;              // single graph: vertex count
+  unsigned long long* qctr;   // claim counter
+  unsigned long long* nlong;  // tasks handed to the item path
+  int64_t* order4;            // their task indices
+  unsigned long long* acc;    // single graph: [16]
+  unsigned long long* gout;   // batched: [graphs][16]
+  const uint32_t* err;
+  ClassSlices cls;
+};
+
+struct GroupLds {
+  uint32_t a[GROUP_W];
+  uint32_t b[GROUP_W];
+  uint32_t hist[16 * 64];  // [class][lane]
+  GroupTask rec[64];       // this sub-batch's grouped tasks, by bin
+};
+
+__device__ void group_flush(GroupLds& L, int lane, unsigned long long* acc) {
+  wave_lds_sync();
+  for (int c = 1; c < 16; ++c) {
+    const uint64_t sum = wave_sum64((uint64_t)(int64_t)(int32_t)L.hist[c * 64 + lane]);
+    if (lane == 0 && sum) atomicAdd(&acc[c], (unsigned long long)sum);
+    L.hist[c * 64 + lane] = 0;
+  }
+  wave_lds_sync();
+}
+
+// One round: GT tasks (records x of lanes' tasks, slots of GROUP_W / GT).
+template <bool BAT, int GT>
+__device__ __forceinline__ void group_round(const GroupArgs& g, GroupLds& L, int lane, const GroupTask& x, bool valid,
+                                            uint32_t& wg, uint32_t& steps) {
+  constexpr int LPT = 64 / GT, STRIDE = GROUP_W / GT, NL = (STRIDE + LPT - 1) / LPT;
+  const int t = lane / LPT, sl = lane % LPT;
+  uint32_t* const A = L.a + t * STRIDE;
+  uint32_t* const B = L.b + t * STRIDE;
+  const uint32_t la = valid ? x.lens & 0xFFFFu : 0u, lb = valid ? x.lens >> 16 : 0u;
+  uint32_t ra[NL], rb[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const uint32_t j = (uint32_t)(sl + k * LPT);
+    ra[k] = j < la ? g.packed[(uint64_t)x.aoff + j] : 0u;
+    rb[k] = j < lb ? g.packed[(uint64_t)x.boff + j] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const uint32_t j = (uint32_t)(sl + k * LPT);
+    if (j < la) A[j] = ra[k];
+    if (j < lb) B[j] = rb[k];
+  }
+  if (sl == 0) {
+    A[la] = KEY_INF;
+    B[lb] = KEY_INF;
+  }
+  wave_lds_sync();
+  bool mixed = false;
+  if constexpr (BAT) {
+    const uint32_t g0 = bcast32(x.gid, 0);
+    mixed = __ballot(valid && x.gid != g0) != 0;
+    if (wg != 0xFFFFFFFFu && (mixed || g0 != wg)) {
+      group_flush(L, lane, g.gout + 16 * (uint64_t)wg);
+      steps = 0;
+    }
+    wg = mixed ? 0xFFFFFFFFu : g0;
+  }
+  // this lane's merge-path share of its task's merge (A before B on equal ids)
+  const uint32_t D = la + lb;
+  const uint32_t d0 = (sl * D) / LPT, d1 = ((sl + 1) * D) / LPT;
+  uint32_t lo = d0 > lb ? d0 - lb : 0, hi = d0 < la ? d0 : la;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (key_of(A[mid]) <= key_of(B[d0 - mid - 1])) lo = mid + 1; else hi = mid;
+  }
+  uint32_t i = lo, k = d0 - lo;
+  if (i > 0 && k < lb && key_of(A[i - 1]) == key_of(B[k])) ++k;  // consumed with A[i-1]
+  const uint32_t f = x.vq & 3u, vq = x.vq | 3u;  // v itself (in N(u)) is never counted
+  const uint64_t slice = f == 3u ? g.cls.s[3] : (f == 2u ? g.cls.s[2] : g.cls.s[1]);
+  for (uint32_t pos = i + k; pos < d1; pos = i + k) {
+    const uint32_t a = A[i], b = B[k];
+    const uint32_t ea = a | 3u, eb = b | 3u;
+    const bool ta = ea <= eb, tb = eb <= ea;
+    // canonical selection (Fig. 5 step 2.1.4), as in the item path
+    const bool cA = ta & (ea > vq);
+    const bool cB = (tb & cA) | (!ta & (eb > x.uq));
+    const uint32_t fa = cA ? a & 3u : 0u, sb = cB ? b : 0u;
+    const uint32_t cls = (uint32_t)(slice >> ((((sb << 2) | fa) << 2) & 63u)) & 15u;
+    atomicAdd(&L.hist[cls * 64 + lane], 1u);
+    i += (uint32_t)ta;
+    k += (uint32_t)tb;
+  }
+  wave_lds_sync();
+  if constexpr (BAT) {
+    if (mixed) {
+      // a round over several graphs: each lane's column to its own task's graph
+      for (int c = 1; c < 16; ++c) {
+        const uint32_t v = L.hist[c * 64 + lane];
+        if (valid && v) atomicAdd(&g.gout[16 * (uint64_t)x.gid + c], (unsigned long long)v);
+        L.hist[c * 64 + lane] = 0;
+      }
+      wave_lds_sync();
+    }
+  }
+  steps += 2 * STRIDE / LPT + 2;
+}
+
+template <bool BAT>
+__global__ void __launch_bounds__(GROUP_WAVES * 64) k_census_grouped(GroupArgs g) {
+  __shared__ GroupLds lds[GROUP_WAVES];
+  if (*g.err) return;
+  const int lane = threadIdx.x & 63;
+  GroupLds& L = lds[threadIdx.x >> 6];
+  for (int c = 0; c < 16; ++c) L.hist[c * 64 + lane] = 0;
+  wave_lds_sync();
+  const uint64_t below = (1ull << lane) - 1;
+  uint32_t wg = 0xFFFFFFFFu;  // graph whose counts the LDS columns hold (batched)
+  uint32_t steps = 0;
+  for (;;) {
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(g.qctr, (unsigned long long)GROUP_CLAIM);
+    base = bcast64(base, 0);
+    if ((int64_t)base >= g.ntasks) break;
+    const int64_t cend = min((int64_t)base + GROUP_CLAIM, g.ntasks);
+    for (int64_t s0 = (int64_t)base; s0 < cend; s0 += 64) {
+      // size this lane's task
+      const int64_t tid = s0 + lane;
+      int bin = -1;
+      GroupTask x{};
+      int32_t dyad = 0;
+      if (tid < cend) {
+        const uint64_t tk = g.tasks[tid];
+        if (tk & HUB_BIT) {
+          bin = 4;  // split: merged from the hub list
+        } else {
+          const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
+          const int64_t au0 = g.off[u], au1 = g.off[u + 1];
+          const uint32_t pv = g.packed[au0 + (uint32_t)tk];
+          const int64_t bv0 = g.off[pv >> 2], bv1 = g.off[(pv >> 2) + 1];
+          const uint32_t sv = min(g.tskip[tid], (uint32_t)(bv1 - bv0));
+          const uint32_t su = g.ustart[u];
+          const uint32_t la = (uint32_t)(au1 - au0) - su, lb = (uint32_t)(bv1 - bv0) - sv;
+          const uint32_t m = max(la, lb);
+          bin = m < (uint32_t)(GROUP_W / 8) ? 0 : m < (uint32_t)(GROUP_W / 4) ? 1 : m < (uint32_t)(GROUP_W / 2) ? 2
+              : m < (uint32_t)GROUP_W ? 3 : 4;
+          x.aoff = (uint32_t)(au0 + su);
+          x.boff = (uint32_t)(bv0 + sv);
+          x.lens = la | lb << 16;
+          x.uq = (u << 2) | 3u;
+          x.vq = pv;
+          int64_t nn = g.n;
+          if (BAT) {
+            x.gid = g.grow[u];
+            nn = g.vbase[x.gid + 1] - g.vbase[x.gid];
+          }
+          if (bin < 4) dyad = (int32_t)(nn - (int64_t)(au1 - au0) - (int64_t)(bv1 - bv0));
+        }
+      }
+      // tasks for the item path: appended to its list
+      {
+        const uint64_t m4 = __ballot(bin == 4);
+        if (m4) {
+          uint64_t at = 0;
+          if (lane == 0) at = atomicAdd(g.nlong, (unsigned long long)__popcll(m4));
+          at = bcast64(at, 0);
+          if (bin == 4) g.order4[at + __popcll(m4 & below)] = tid;
+        }
+      }
+      // the dyadic terms n - d(u) - d(v) of the grouped tasks (Fig. 5 step
+      // 2.1.3; the common-neighbour part is added at the end)
+      {
+        const bool mut = (x.vq & 3u) == 3u;
+        const uint32_t g0 = bcast32(x.gid, 0);
+        if (!BAT || __ballot(dyad != 0 && x.gid != g0) == 0) {
+          const uint64_t sa = wave_sum64(mut ? 0 : (uint64_t)(int64_t)dyad);
+          const uint64_t sm = wave_sum64(mut ? (uint64_t)(int64_t)dyad : 0);
+          unsigned long long* tgt = BAT ? g.gout + 16 * (uint64_t)g0 : g.acc;
+          if (lane == 0) {
+            if (sa) atomicAdd(&tgt[1], (unsigned long long)sa);
+            if (sm) atomicAdd(&tgt[2], (unsigned long long)sm);
+          }
+        } else if (dyad != 0) {
+          atomicAdd(&g.gout[16 * (uint64_t)x.gid + (mut ? 2 : 1)], (unsigned long long)(int64_t)dyad);
+        }
+      }
+      // the grouped tasks into LDS, bin by bin
+      uint32_t nb[4], sb[4];
+      uint32_t run = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t mq = __ballot(bin == q);
+        if (bin == q) L.rec[run + __popcll(mq & below)] = x;
+        nb[q] = (uint32_t)__popcll(mq);
+        sb[q] = run;
+        run += nb[q];
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int GTq = 8 >> q;
+        for (uint32_t r = 0; r < nb[q]; r += (uint32_t)GTq) {
+          const uint32_t slot = (uint32_t)(lane / (64 / GTq));
+          const bool valid = r + slot < nb[q];
+          GroupTask y{};
+          if (valid) y = L.rec[sb[q] + r + slot];
+          if (q == 0) group_round<BAT, 8>(g, L, lane, y, valid, wg, steps);
+          else if (q == 1) group_round<BAT, 4>(g, L, lane, y, valid, wg, steps);
+          else if (q == 2) group_round<BAT, 2>(g, L, lane, y, valid, wg, steps);
+          else group_round<BAT, 1>(g, L, lane, y, valid, wg, steps);
+        }
+      }
+      wave_lds_sync();
+      if (steps > (1u << 30)) {
+        if (!BAT || wg != 0xFFFFFFFFu) group_flush(L, lane, BAT ? g.gout + 16 * (uint64_t)wg : g.acc);
+        steps = 0;
+      }
+    }
+  }
+  if (!BAT || wg != 0xFFFFFFFFu) group_flush(L, lane, BAT ? g.gout + 16 * (uint64_t)wg : g.acc);
 }
 
 // The dyadic counts (Fig. 5 step 2.1.3) need each task's number of common
@@ -1439,49 +1741,71 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
 // into one disjoint union; a task never leaves its graph, so the single-graph
 // kernels apply unchanged except that each graph keeps its own counters.
 
-// Per row (thread per row): graph of the row, offset checks, local id checks,
-// packed words with global ids, first entry above the row, task count.
+// Per row of a batch: its graph, offset checks, the first entry above the
+// row (binary search over its graph-local ids), the self-loop check, the task
+// count and the row-start mark.
 __global__ void k_rows_batch(int32_t G, int64_t nv, int64_t nnz, const int64_t* __restrict__ vbase,
                              const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
-                             const uint8_t* __restrict__ flg, uint32_t* __restrict__ grow,
-                             uint32_t* __restrict__ ustart, int64_t* __restrict__ ntask, uint32_t* __restrict__ packed,
-                             uint32_t* __restrict__ err) {
+                             uint32_t* __restrict__ grow, uint32_t* __restrict__ ustart, int64_t* __restrict__ ntask,
+                             uint32_t* __restrict__ rowmark, uint32_t* __restrict__ err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < nv; u += stride) {
-    uint32_t bits = 0;
     int32_t lo = 0, hi = G;  // last graph with vbase[g] <= u
     while (hi - lo > 1) {
       const int32_t mid = (lo + hi) >> 1;
       if (vbase[mid] <= u) lo = mid; else hi = mid;
     }
-    const int64_t g0 = vbase[lo], ng = vbase[lo + 1] - g0;
     grow[u] = (uint32_t)lo;
+    const int64_t g0 = vbase[lo];
     const int64_t b = off[u], e = off[u + 1];
-    if (u == 0 && b != 0) bits |= ERR_RANGE;
-    if (u == nv - 1 && e != nnz) bits |= ERR_RANGE;
     ustart[u] = 0;
     ntask[u] = 0;
-    if (e < b || b < 0 || e > nnz) {
-      atomicOr(err, bits | ERR_RANGE);
+    if ((u == 0 && b != 0) || (u == nv - 1 && e != nnz) || e < b || b < 0 || e > nnz) {
+      atomicOr(err, ERR_RANGE);
       continue;
     }
     const int32_t ul = (int32_t)(u - g0);
-    int64_t first = e;
-    int32_t prev = -1;
-    for (int64_t j = b; j < e; ++j) {
+    int64_t p = b, q = e;  // first entry with a local id above ul
+    while (p < q) {
+      const int64_t m = (p + q) >> 1;
+      if (nbr[m] <= ul) p = m + 1; else q = m;
+    }
+    if (p > b && nbr[p - 1] == ul) atomicOr(err, ERR_SELFLOOP);
+    ustart[u] = (uint32_t)(p - b);
+    ntask[u] = e - p;
+    if (e > b) atomicOr(&rowmark[b >> 5], 1u << (b & 31));
+  }
+}
+
+// Per entry of a batch: graph-local id in range, flag not 0, rows strictly
+// increasing, and the packed word with the id moved to the disjoint union
+// (graph base added).
+__global__ void __launch_bounds__(256) k_entries_batch(int64_t nv, int64_t nnz, const int64_t* __restrict__ vbase,
+                                                       const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
+                                                       const uint8_t* __restrict__ flg, const uint32_t* __restrict__ grow,
+                                                       const uint32_t* __restrict__ rowmark,
+                                                       uint32_t* __restrict__ packed, uint32_t* __restrict__ err) {
+  __shared__ int64_t rr[2];
+  uint32_t bits = 0;
+  for (int64_t t0 = (int64_t)blockIdx.x * ETILE; t0 < nnz; t0 += (int64_t)gridDim.x * ETILE) {
+    const int64_t t1 = min(t0 + (int64_t)ETILE, nnz);
+    tile_rows(off, nv, t0, t1, rr);
+    const int64_t r0 = rr[0], r1 = rr[1];
+    for (int64_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
+      const int64_t x = row_search(off, r0, r1 + 1, j);
+      const uint32_t gx = grow[x];
+      const int64_t g0 = vbase[gx], ng = vbase[gx + 1] - g0;
       const int32_t y = nbr[j];
       const uint32_t f = (flg[j >> 2] >> (2 * (j & 3))) & 3u;
-      if (y < 0 || y >= ng || f == 0) { bits |= ERR_RANGE; break; }
-      if (y <= prev) bits |= ERR_UNSORTED;
-      if (y == ul) bits |= ERR_SELFLOOP;
-      if (y > ul && first == e) first = j;
-      prev = y;
+      if (y < 0 || y >= ng || f == 0) bits |= ERR_RANGE;
+      if (j + 1 < nnz) {
+        const bool row_start = (rowmark[(j + 1) >> 5] >> ((j + 1) & 31)) & 1u;
+        if (!row_start && nbr[j + 1] <= y) bits |= ERR_UNSORTED;
+      }
       packed[j] = ((uint32_t)(y + g0) << 2) | f;
     }
-    ustart[u] = (uint32_t)(first - b);
-    ntask[u] = e - first;
-    if (bits) atomicOr(err, bits);
   }
+  if (bits) atomicOr(err, bits);
 }
 
 __global__ void k_check_tasks(const int64_t* __restrict__ tpre, int64_t nv, int64_t nnz, uint32_t* __restrict__ err) {
@@ -1540,6 +1864,18 @@ __global__ void k_batch_signature(int32_t G, int64_t nv, const int64_t* __restri
     atomicAdd(&sig[0], (unsigned long long)h);
     atomicAdd(&sig[1], (unsigned long long)s2);
   }
+}
+
+// Persistent grid of a grouped-task kernel: every workgroup resident.
+template <bool BAT>
+static int group_grid() {
+  DeviceInfo di;
+  if (device_info(&di) != TRIAD_OK) return 1024;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census_grouped<BAT>, GROUP_WAVES * 64, 0) !=
+          hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return di.cus * per_cu;
 }
 
 // Three-pass exclusive scan with caller-provided block sums (capturable).
@@ -1629,16 +1965,20 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   p->nnz = nnz;
   p->vbase = vbase;
   p->out = d_out;
-  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr, *tskip = nullptr;
+  uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr, *tskip = nullptr, *rowmark = nullptr;
   uint64_t* long_segs = nullptr;
   int64_t *ntask = nullptr, *tpre = nullptr, *bsum = nullptr;
   uint64_t* tasks = nullptr;
-  unsigned long long* q = nullptr;
+  unsigned long long* q = nullptr;  // census queue [2], long rows, grouped bins [3]
   const int64_t ntasks = nnz / 2;
-  if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 3) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
+  // short tasks run grouped (task records hold 32-bit entry offsets)
+  const bool grouped = ntasks > 0 && nnz + PAD < ((int64_t)1 << 32) && o.short_tasks >= 0;
+  int64_t* order4 = nullptr;
+  if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 6) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
       plan_alloc(p, &ntask, nv) || plan_alloc(p, &tpre, nv + 1) || plan_alloc(p, &bsum, nv / SCAN_B + 2) ||
       plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks) || plan_alloc(p, &tskip, ntasks) ||
-      plan_alloc(p, &long_segs, emit_seg_cap(nv, ntasks))) {
+      plan_alloc(p, &long_segs, emit_seg_cap(nv, ntasks)) || plan_alloc(p, &rowmark, (nnz >> 5) + 1) ||
+      (grouped && plan_alloc(p, &order4, ntasks))) {
     plan_free(p);
     (void)hipGetLastError();
     return fail(TRIAD_ENOMEM, "device allocation for the batch plan failed");
@@ -1680,18 +2020,45 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   }
   s = cs;
   k_fill_u32<<<1, 64, 0, s>>>(p->err, 1, 0);
-  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)q, 3, 0);  // queue counters, long rows
+  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)q, 6, 0);  // queue counters, long rows, grouped bins
   k_fill_u64<<<grid_for((int64_t)G * 16, 256, 4096), 256, 0, s>>>(d_out, (int64_t)G * 16, 0);
   if (nv > 0) {
-    k_rows_batch<<<grid_for(nv, 256, 65535), 256, 0, s>>>(G, nv, nnz, vbase, off, nbr, flg, grow, ustart, ntask, packed,
+    k_fill_u32<<<grid_for((nnz >> 5) + 1, 256, 4096), 256, 0, s>>>(rowmark, (nnz >> 5) + 1, 0);
+    k_rows_batch<<<grid_for(nv, 256, 65535), 256, 0, s>>>(G, nv, nnz, vbase, off, nbr, grow, ustart, ntask, rowmark,
                                                           p->err);
+    if (nnz > 0)
+      k_entries_batch<<<grid_for(nnz, ETILE, 65536), 256, 0, s>>>(nv, nnz, vbase, off, nbr, flg, grow, rowmark, packed,
+                                                                 p->err);
     scan_excl_pre(ntask, nv, tpre, bsum, s);
     k_check_tasks<<<1, 64, 0, s>>>(tpre, nv, nnz, p->err);
     if (ntasks > 0) {
-      // small graphs: the search for the ids of N(v) below u would cost more
-      // than it saves
-      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, 0, -1, long_segs, q + 2, p->err};
-      launch_emit(ea, s);
+      // the ids of N(v) below u are counted (the merge starts N(v) at u) when
+      // the short tasks run grouped, where every merged entry weighs
+      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, grouped ? 1 : 0, -1, long_segs, q + 2, p->err};
+      launch_emit_entries(ea, nnz, s);
+      if (grouped) {
+        GroupArgs ga{};
+        ga.off = off;
+        ga.packed = packed;
+        ga.ustart = ustart;
+        ga.tskip = tskip;
+        ga.tasks = tasks;
+        ga.ntasks = ntasks;
+        ga.grow = grow;
+        ga.vbase = vbase;
+        ga.n = 0;
+        ga.qctr = q + 3;
+        ga.nlong = q + 4;
+        ga.order4 = order4;
+        ga.acc = nullptr;
+        ga.gout = (unsigned long long*)d_out;
+        ga.err = p->err;
+        ga.cls = class_slices();
+        k_census_grouped<true><<<group_grid<true>(), GROUP_WAVES * 64, 0, s>>>(ga);
+        // the rest through the item path, in CSR order
+        a.order = order4;
+        a.ntasks_dev = (const int64_t*)(q + 4);
+      }
       (void)launch_census(waves, variant, a, groups, s);
     }
   }

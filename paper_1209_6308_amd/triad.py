@@ -62,7 +62,7 @@ class Opts(ctypes.Structure):
                 ("chunk", ctypes.c_int64), ("model", ctypes.c_void_p), ("task_cycles", ctypes.c_void_p),
                 ("timing", ctypes.POINTER(Timing)), ("waves_per_group", ctypes.c_int32),
                 ("grid_groups", ctypes.c_int32), ("kernel_variant", ctypes.c_int32),
-                ("wave_span", ctypes.c_void_p), ("tail_share", ctypes.c_int32)]
+                ("wave_span", ctypes.c_void_p), ("tail_share", ctypes.c_int32), ("short_tasks", ctypes.c_int32)]
 
 
 _LIB = None
@@ -142,7 +142,8 @@ def _stream(stream=None):
 
 
 def make_opts(schedule="plain", validate=0, hub_threshold=0, chunk=0, model=None, task_cycles=None,
-              waves_per_group=0, grid_groups=0, timing=None, wave_span=None, kernel_variant=0, tail_share=0):
+              waves_per_group=0, grid_groups=0, timing=None, wave_span=None, kernel_variant=0, tail_share=0,
+              short_tasks=0):
     o = Opts()
     o.schedule = SCHED[schedule] if isinstance(schedule, str) else int(schedule)
     o.validate = validate
@@ -155,6 +156,7 @@ def make_opts(schedule="plain", validate=0, hub_threshold=0, chunk=0, model=None
     o.kernel_variant = kernel_variant
     o.wave_span = wave_span.data_ptr() if wave_span is not None else None
     o.tail_share = tail_share
+    o.short_tasks = short_tasks
     if timing is not None:
         o.timing = ctypes.pointer(timing)
     return o

@@ -42,12 +42,35 @@ def concat(members):
                            np.zeros((len(members), 6)))
 
 
-def test_small_ensemble(torch):
+@pytest.mark.parametrize("short_tasks", [0, -1])
+def test_small_ensemble(torch, short_tasks):
     B = graphs.null_ensemble(G=48, seed=5, nmin=64, nmax=700, dmin=4, dmax=20)
     d = triad.batch_to_device(B)
-    got = triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d)
+    got = triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d, short_tasks=short_tasks)
     for g in range(B.G):
         assert got[g] == oracle.census(B.graph(g)), g
+
+
+def test_grouped_rounds_across_graphs(torch):
+    """Many tiny members: grouped rounds of short tasks span graph boundaries
+    (each lane's counts go to its own task's graph), next to members whose
+    tasks fill every bin and the item path (a star with a 300-leaf hub)."""
+    members = []
+    rng = np.random.default_rng(12)
+    for k in range(300):
+        n = int(rng.integers(3, 9))
+        s, t = random_digraph(n, 0.6, 0.3, 1000 + k)
+        members.append(graphs.build_csr(n, s, t))
+    star = [(0, j) for j in range(1, 301)] + [(j, j + 1) for j in range(1, 300, 3)]
+    members.append(graphs.from_arcs(302, star))
+    for n, dens in ((120, 0.5), (260, 0.9), (40, 0.2)):
+        s, t = random_digraph(n, dens, 0.2, n)
+        members.append(graphs.build_csr(n, s, t))
+    B = concat(members)
+    d = triad.batch_to_device(B)
+    got = triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d)
+    for g, m in enumerate(members):
+        assert got[g] == oracle.census(m), g
 
 
 def test_degenerate_members(torch):
@@ -173,5 +196,6 @@ def test_full_ensemble_golden(torch):
                              dmax=p["dmax"], rmax=p["rmax"], swap_factor=p["swap_factor"])
     assert B.content_hash() == rec["content_hash"]
     d = triad.batch_to_device(B)
-    got = triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d)
-    assert [[str(x) for x in row] for row in got] == rec["census"]
+    for short_tasks in (0, -1):
+        got = triad.triad_census_batch(B.G, int(B.vbase[-1]), B.nnz, *d, short_tasks=short_tasks)
+        assert [[str(x) for x in row] for row in got] == rec["census"], short_tasks
