@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--no-schedules", action="store_true", help="skip the heuristic / learned comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched null-model ensemble comparison")
     ap.add_argument("--no-cl22", action="store_true", help="skip the schedule comparison on the Chung-Lu graph")
+    ap.add_argument("--no-adjacent", action="store_true",
+                    help="skip the CSR construction, incremental, labelled and significance-profile legs")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
@@ -196,8 +198,15 @@ def main():
         if args.workload != "cl22" and not args.no_cl22:
             rec["schedules_cl22"] = compare_schedules(torch, graphs, triad, "cl22", min(args.steps, 5), stream,
                                                       models)
+    if not args.no_adjacent:
+        rec["csr_build"] = csr_build_bench(torch, graphs, triad, args.workload, (d_off, d_nbr, d_flg))
+        rec["incremental"] = incremental_bench(torch, triad, g, (d_off, d_nbr, d_flg), counts, stream)
+        rec["labelled"] = labelled_bench(torch, triad, g, (d_off, d_nbr, d_flg), counts, stream,
+                                         sum(main["census_ms"]) / len(main["census_ms"]))
     if not args.no_batched:
         rec["batched"] = batched_bench(torch)
+    if not args.no_adjacent:
+        rec["significance"] = significance_bench(torch, graphs, triad)
     if not args.no_cpu_baseline:
         log("timing the oracle on a task sample (host cores)")
         rec["cpu_baseline"] = cpu_baseline(g)
@@ -281,6 +290,137 @@ def compare_schedules(torch, graphs, triad, name, steps, stream, models):
     out["identical_counts"] = True
     out["census"] = [str(x) for x in counts]
     return out
+
+
+def csr_build_bench(torch, graphs, triad, name, dev, reps=3):
+    """The CSR with direction flags built on the device from the workload's raw
+    arc list (duplicates and self-loops included), against the host build the
+    generator does; the result must equal the resident CSR."""
+    w = graphs.WORKLOADS[name]
+    if w["kind"] != "rmat" or w.get("recip_p"):
+        return None
+    n = 1 << w["scale"]
+    t0 = time.perf_counter()
+    src, dst = graphs.rmat_arcs(w["scale"], w["edge_factor"] * n, seed=w["seed"])
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    host = graphs.build_csr(n, src, dst)
+    host_s = time.perf_counter() - t0
+    del host
+    ds, dd = torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda()
+    narcs = src.size
+    del src, dst
+    ms = []
+    for i in range(reps):
+        off, nbr, flg, t = triad.csr_from_arcs(n, ds, dd, timed=True)
+        ms.append(t)
+        log(f"csr build {i + 1}/{reps}: {t:.1f} ms")
+    same = bool(torch.equal(off, dev[0]) and torch.equal(nbr, dev[1]) and torch.equal(flg, dev[2]))
+    if not same:
+        raise SystemExit("device CSR construction differs from the host build")
+    del off, nbr, flg, ds, dd
+    torch.cuda.empty_cache()
+    best = min(ms)
+    return {"workload": f"{name} raw arcs ({narcs} drawn, duplicates and self-loops included)",
+            "device_ms": round(best, 2), "device_ms_all": [round(x, 2) for x in ms],
+            "arcs_per_s": round(narcs / (best / 1e3), 1), "host_build_s": round(host_s, 2),
+            "host_threads": graphs.nthreads(), "arc_generation_s": round(gen_s, 2),
+            "speedup_vs_host": round(host_s / (best / 1e3), 1), "identical_csr": same}
+
+
+def incremental_bench(torch, triad, g, dev, census, stream, batches=8, k=100000, seed=5):
+    """Census of the workload under batches of arc updates (half deletions of
+    present arcs, half insertions between random vertices, in order), each
+    batch's census from the previous one; the last is checked against a full
+    census of the final graph."""
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    off, nbr, flg = dev
+    n, nnz = g.n, g.nnz
+    ms, changed, c = [], [], census
+    for b in range(batches):
+        # deletions: arcs present in the CSR (an entry whose bit0 is set is the arc row -> id)
+        j = torch.randint(0, nnz, (k // 2,), device="cuda", generator=gen)
+        f = (flg[j >> 2].to(torch.int64) >> (2 * (j & 3))) & 3
+        rows = torch.searchsorted(off, j, right=True) - 1
+        cols = nbr[j].to(torch.int64)
+        out_arc = (f & 1) != 0
+        dsrc = torch.where(out_arc, rows, cols)
+        ddst = torch.where(out_arc, cols, rows)
+        isrc = torch.randint(0, n, (k - k // 2,), device="cuda", generator=gen)
+        idst = (isrc + torch.randint(1, n, (k - k // 2,), device="cuda", generator=gen)) % n
+        usrc = torch.cat([dsrc, isrc]).to(torch.int32)
+        udst = torch.cat([ddst, idst]).to(torch.int32)
+        perm = torch.randperm(k, device="cuda", generator=gen)
+        usrc, udst = usrc[perm].contiguous(), udst[perm].contiguous()
+        uins = torch.cat([torch.zeros(k // 2, dtype=torch.uint8, device="cuda"),
+                          torch.ones(k - k // 2, dtype=torch.uint8, device="cuda")])[perm].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, new, chg = triad.census_update(n, nnz, off, nbr, flg, c, usrc, udst, uins, stream=stream)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+        changed.append(chg)
+        off, nbr, flg = new
+        nnz = int(nbr.numel())
+        log(f"incremental batch {b + 1}/{batches}: {ms[-1]:.1f} ms, {chg} changed pairs")
+    full, _, tm = triad.triad_census_device(n, nnz, off, nbr, flg, stream=stream)
+    if full != c:
+        raise SystemExit("incremental census differs from the full census of the final graph")
+    mean = sum(ms[1:]) / max(1, len(ms) - 1)
+    return {"workload": f"{g.name}: {batches} batches of {k} arc updates (half deletions of present arcs, half "
+                        f"insertions between random vertices, shuffled)",
+            "batch_ms": [round(x, 2) for x in ms], "mean_batch_ms": round(mean, 2),
+            "updates_per_s": round(k / (mean / 1e3), 1), "changed_pairs": changed,
+            "full_census_ms_final_graph": round(tm["census_ms"] + tm["tasks_ms"] + tm["prep_ms"], 2),
+            "identical_to_full_census": True}
+
+
+def labelled_bench(torch, triad, g, dev, counts, stream, census16_ms, reps=2):
+    """The 64-state labelled census of the workload (its states must add up to
+    C(n,3); the GPU tests check that they condense to the 16-class census)."""
+    ms, lab = [], None
+    for i in range(reps):
+        lab, st, tm = triad.labelled_census_device(g.n, g.nnz, *dev, stream=stream)
+        ms.append(tm["census_ms"])
+        log(f"labelled census {i + 1}/{reps}: kernel {tm['census_ms']:.1f} ms")
+    return {"workload": g.name, "census_kernel_ms": round(min(ms), 2),
+            "edge_pairs_per_s_kernel": round(g.nnz // 2 / (min(ms) / 1e3), 1),
+            "census16_kernel_ms": round(census16_ms, 2),
+            "state_sum_equals_C(n,3)": sum(lab) == g.n * (g.n - 1) * (g.n - 2) // 6,
+            "states": [str(x) for x in lab]}
+
+
+def significance_bench(torch, graphs, triad, scale=12, K=1024):
+    """Triad significance profile of an R-MAT graph against K degree-preserving
+    randomisations: one batched census of the ensemble plus the z-score kernel."""
+    g = graphs.rmat(scale, 8, seed=3, recip_p=0.1)
+    t0 = time.perf_counter()
+    B = graphs.randomised_ensemble(g, K, seed=1)
+    gen_s = time.perf_counter() - t0
+    d = triad.batch_to_device(B)
+    real_d = triad.to_device(g)
+    real = triad.triad_census_device(g.n, g.nnz, *real_d)[0]
+    out = torch.empty((B.G, 16), dtype=torch.int64, device="cuda")
+    plan = triad.BatchPlan(B.G, int(B.vbase[-1]), B.nnz, *d, d_out=out)
+    plan.launch()
+    plan.status()
+    ts = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.launch()
+        z, sp = triad.significance_profile(out, real)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    plan.close()
+    best = min(ts)
+    m_sym = B.nnz // 2
+    return {"workload": f"R-MAT scale {scale}, edge factor 8, 10% reciprocated, seed 3; {K} randomisations "
+                        "(10 x arcs double-edge swap attempts each)",
+            "ms": round(best * 1e3, 2), "ensemble_edge_pairs_per_s": round(m_sym / best, 1),
+            "ensemble_generation_s_host": round(gen_s, 1), "z": [round(x, 4) for x in z],
+            "profile": [round(x, 4) for x in sp]}
 
 
 def census_roofline(workload, kern_s, d_off, d_nbr, n, st):

@@ -413,6 +413,10 @@ static void launch_emit_entries(const EmitArgs& e, int64_t nnz, hipStream_t s) {
 
 // ------------------------------------------------------------ the census
 
+// Longest list (entries) of a task merged by the grouped-task kernel (one
+// LDS window of it per list).
+constexpr int GROUP_W = 448;
+
 struct CensusArgs {
   int64_t n;
   const int64_t* off;
@@ -1084,7 +1088,6 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
 // whose longer list fits a slot for GT = 8, 4, 2 or 1 are sorted by that fit
 // (bin 0..3) into an LDS list and run GT per round; bin 4 (longer, or split)
 // is appended to a list the item path takes afterwards.
-constexpr int GROUP_W = 448;
 constexpr int GROUP_WAVES = 2;
 constexpr int GROUP_CLAIM = 1024;  // tasks per claim: claims of a shared counter must stay rare
 __host__ __device__ constexpr int group_tasks(int bin) { return 8 >> bin; }  // tasks per round of bins 0..3
@@ -1234,9 +1237,7 @@ __global__ void __launch_bounds__(GROUP_WAVES * 64) k_census_grouped(GroupArgs g
       int32_t dyad = 0;
       if (tid < cend) {
         const uint64_t tk = g.tasks[tid];
-        if (tk & HUB_BIT) {
-          bin = 4;  // split: merged from the hub list
-        } else {
+        if (!(tk & HUB_BIT)) {  // split tasks are merged from the hub list
           const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu;
           const int64_t au0 = g.off[u], au1 = g.off[u + 1];
           const uint32_t pv = g.packed[au0 + (uint32_t)tk];
@@ -1261,7 +1262,7 @@ __global__ void __launch_bounds__(GROUP_WAVES * 64) k_census_grouped(GroupArgs g
         }
       }
       // tasks for the item path: appended to its list
-      {
+      if (g.order4) {
         const uint64_t m4 = __ballot(bin == 4);
         if (m4) {
           uint64_t at = 0;
@@ -1468,6 +1469,18 @@ static hipError_t launch_census(int waves, int variant, const CensusArgs& a, int
   }
 }
 
+// Persistent grid of a grouped-task kernel: every workgroup resident.
+template <bool BAT>
+static int group_grid() {
+  DeviceInfo di;
+  if (device_info(&di) != TRIAD_OK) return 1024;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census_grouped<BAT>, GROUP_WAVES * 64, 0) !=
+          hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return di.cus * per_cu;
+}
+
 // The labelled census (64 counters per column: 8 KB of LDS per wavefront)
 // runs one launch shape: 448-entry windows, two wavefronts per workgroup.
 constexpr int LAB_WAVES = 2;
@@ -1543,7 +1556,7 @@ struct Events {
 static size_t census_scratch_bound(int64_t n, int64_t nnz) {
   const int64_t m = nnz / 2;
   auto r = [](int64_t bytes) { return (size_t)((std::max<int64_t>(bytes, 1) + 255) & ~(int64_t)255); };
-  size_t b = r(4) + r(20 * 8);
+  size_t b = r(4) + r((16 + 5) * 8);  // errors; counters, queues
   if (n > 0) {
     b += r(4 * n) + r(8 * n) + r(8 * (n + 1)) + r(4 * ((nnz >> 5) + 1)) + r(4 * (nnz + PAD));
     b += r(8 * ((n + SCAN_B - 1) / SCAN_B + 1));
@@ -1593,11 +1606,12 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   if (o.timing) HIPCHK(ev.init());
   Scratch scratch = arena ? Scratch(s, arena, arena_bytes) : Scratch(s);
   uint32_t* err = nullptr;
-  unsigned long long* acc = nullptr;  // NC census counters, 2 queue counters, hub tasks, long rows
+  // NC census counters, 2 queue counters, hub tasks, long rows, grouped-task claims
+  unsigned long long* acc = nullptr;
   ALLOC(err, 1);
-  ALLOC(acc, NC + 4);
+  ALLOC(acc, NC + 5);
   k_fill_u32<<<1, 64, 0, s>>>(err, 1, 0);
-  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)acc, NC + 4, 0);
+  k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)acc, NC + 5, 0);
   uint64_t clo, chi;
   choose3(n, &clo, &chi);
   ev.rec(0, s);
@@ -1864,18 +1878,6 @@ __global__ void k_batch_signature(int32_t G, int64_t nv, const int64_t* __restri
     atomicAdd(&sig[0], (unsigned long long)h);
     atomicAdd(&sig[1], (unsigned long long)s2);
   }
-}
-
-// Persistent grid of a grouped-task kernel: every workgroup resident.
-template <bool BAT>
-static int group_grid() {
-  DeviceInfo di;
-  if (device_info(&di) != TRIAD_OK) return 1024;
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census_grouped<BAT>, GROUP_WAVES * 64, 0) !=
-          hipSuccess || per_cu < 1)
-    per_cu = 1;
-  return di.cus * per_cu;
 }
 
 // Three-pass exclusive scan with caller-provided block sums (capturable).
