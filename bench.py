@@ -289,6 +289,11 @@ def compare_schedules(torch, graphs, triad, name, steps, stream, models):
         out[sched] = schedule_summary(r, st["m_sym"], b_alg)
     out["identical_counts"] = True
     out["census"] = [str(x) for x in counts]
+    if "learned" in models:
+        # the network trained on R-MAT scale 10 and 20 cycles, evaluated on this graph's
+        from paper_1209_6308_amd import costmodel
+        out["cost_model_held_out"] = costmodel.held_out_report(models["learned"], g, stream=stream)
+        log(f"cost model on {name} (held out): {out['cost_model_held_out']}")
     return out
 
 

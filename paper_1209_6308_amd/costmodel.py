@@ -104,15 +104,46 @@ def training_set(names=("rmat10", "rmat20"), max_samples=1 << 21, seed=3, device
     return X.contiguous(), t.contiguous()
 
 
-def affine_baseline_mse(X, t):
-    """Mean squared error of the best affine predictor of log2 cycles from
-    log2(1 + d(u) + d(v)) (the heuristic's key), fitted by least squares."""
+def affine_fit(X, t):
+    """Least-squares coefficients (slope, intercept) of the best affine
+    predictor of log2 cycles from log2(1 + d(u) + d(v)), the heuristic's key."""
     x = X[:, 2].double().cpu().numpy()
     y = t.double().cpu().numpy()
     A = np.stack([x, np.ones_like(x)], axis=1)
     coef, *_ = np.linalg.lstsq(A, y, rcond=None)
-    r = A @ coef - y
+    return coef
+
+
+def affine_mse(coef, X, t):
+    x = X[:, 2].double().cpu().numpy()
+    r = coef[0] * x + coef[1] - t.double().cpu().numpy()
     return float(np.mean(r * r))
+
+
+def affine_baseline_mse(X, t):
+    """Mean squared error of the best affine predictor of log2 cycles from
+    log2(1 + d(u) + d(v)) (the heuristic's key), fitted on the same samples."""
+    return affine_mse(affine_fit(X, t), X, t)
+
+
+def model_mse(w, X, t, stream=None):
+    """Mean squared error of the network's predicted log2 cycles."""
+    return float(((forward(w, X, stream) - t) ** 2).double().mean().item())
+
+
+def held_out_report(w, g, stream=None):
+    """The trained network and the affine fit of the training samples, both
+    evaluated on the per-task cycles of another graph g (not trained on)."""
+    import torch
+    e = next((v for (dev, ep), v in _CACHE.items()), None)
+    cyc = record_cycles(g, stream=stream)
+    X = features(g, stream=stream)
+    keep = cyc > 0
+    X, t = X[keep].contiguous(), torch.log2(cyc[keep].double()).float().contiguous()
+    out = {"graph": g.name, "tasks": int(X.shape[0]), "network_mse": model_mse(w, X, t, stream)}
+    if e is not None and len(e) > 3:
+        out["affine_dudv_mse"] = affine_mse(e[3], X, t)
+    return out
 
 
 def load_or_train(stream=None, device="cuda", epochs=30):
@@ -122,7 +153,8 @@ def load_or_train(stream=None, device="cuda", epochs=30):
     if key not in _CACHE:
         X, t = training_set(device=device, stream=stream)
         w, hist = train(X, t, epochs=epochs, stream=stream)
-        _CACHE[key] = (w, hist, affine_baseline_mse(X, t))
+        coef = affine_fit(X, t)
+        _CACHE[key] = (w, hist, affine_mse(coef, X, t), coef)
     return _CACHE[key][0]
 
 

@@ -1,7 +1,7 @@
 // Directed triad census on CDNA4 (gfx950): kernels and the single-graph
 // pipeline behind triad_census_device().
 //
-// Pipeline (one HIP stream, no host synchronisation until the end):
+// Pipeline (one HIP stream; the host reads two sizes on the way):
 //   k_rows      per row u: offset checks, first entry > u (binary search on the
 //               sorted row), self-loop check, tasks(u) = entries above u
 //   k_entries   per entry: neighbour/flag checks, sortedness, and the packed
@@ -9,14 +9,17 @@
 //               Sec. 6 / Fig. 7, built once on the device)
 //   scan        exclusive prefix of tasks(u): the collapsed (u,v) task space
 //               of Fig. 5 steps 2 and 2.1
-//   k_emit_*    task list in CSR order (short rows one lane each, long rows in
-//               segments, one wavefront each) with each task's count of N(v)
-//               ids below u; tasks whose merge length d(u)+d(v) exceeds the
-//               hub threshold go to the hub list instead
+//   k_emit_entries  task list in CSR order, one thread per entry, with each
+//               task's count of N(v) ids below u; tasks whose merge length
+//               d(u)+d(v) exceeds the hub threshold are flagged, and k_hub_list
+//               lists them
 //   k_census    persistent wavefronts: hub chunks first, then tasks; each
 //               item merges a range of N(u) with a range of N(v)
 //   k_finalize  the common-neighbour part of 012 and 102 from the triangle
 //               classes; 003 = C(n,3) - sum of the rest, in two 64-bit words
+// The batched census (many graphs in one captured launch) and the labelled
+// (64-state) census use the same kernels; short tasks of a batch run several
+// to a round in k_census_grouped.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -204,18 +207,9 @@ __global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t m, const in
 // --------------------------------------------------------------- task list
 
 // Task list in CSR order: the tasks of row u are its entries above u, written
-// as (u << 32 | local index); tasks longer than the hub threshold are flagged.
-// Rows with at most EMIT_SHORT tasks are emitted by one lane each
-// (k_emit_short, which lists the longer rows cut into segments of at most
-// EMIT_SEG tasks); each segment by a whole wavefront (k_emit_long), so that no
-// wavefront walks a hub row of 10^5 tasks alone. The hub list is compacted
-// afterwards (k_hub_list).
-constexpr int64_t EMIT_SHORT = 32;
-constexpr int64_t EMIT_SEG = 1024;
-
-// Capacity of the segment list for a task list of ntasks tasks over n rows.
-static inline int64_t emit_seg_cap(int64_t n, int64_t ntasks) { return n + ntasks / EMIT_SEG + 1; }
-
+// as (u << 32 | local index), each with its count of N(v) ids below u; tasks
+// longer than the hub threshold are flagged and listed afterwards
+// (k_hub_list, one atomic per tile of tasks).
 struct EmitArgs {
   int64_t n;
   const int64_t* off;
@@ -226,8 +220,6 @@ struct EmitArgs {
   uint32_t* tskip;        // per task: entries of N(v) below u
   int32_t count_below;    // 0: write 0 to tskip (the merge then takes all of N(v))
   int64_t hub_threshold;  // < 0: no hub tasks
-  uint64_t* long_segs;  // u << 32 | segment index within the row
-  unsigned long long* long_count;
   const uint32_t* err;
 };
 
@@ -256,60 +248,6 @@ __device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int64_t u
     }
   }
   e.tskip[t] = lo;
-}
-
-__global__ void k_emit_short(EmitArgs e) {
-  if (*e.err) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t ub = wave * 64; ub < e.n; ub += nwave * 64) {
-    const int64_t u = ub + lane;
-    int64_t b = 0, du = 0, t0 = 0, cnt = 0;
-    uint32_t s = 0;
-    if (u < e.n) {
-      b = e.off[u];
-      du = e.off[u + 1] - b;
-      s = e.ustart[u];
-      t0 = e.tpre[u];
-      cnt = du - s;
-    }
-    const bool lng = cnt > EMIT_SHORT;
-    if (__ballot(lng)) {
-      // segments of this lane's row, placed after those of the lower lanes
-      const uint32_t ns = lng ? (uint32_t)((cnt + EMIT_SEG - 1) / EMIT_SEG) : 0u;
-      uint32_t inc = ns;
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(inc, d);
-        if (lane >= d) inc += y;
-      }
-      uint64_t base = 0;
-      if (lane == 63) base = atomicAdd(e.long_count, (unsigned long long)inc);
-      base = bcast64(base, 63) + (inc - ns);
-      for (uint32_t j = 0; j < ns; ++j) e.long_segs[base + j] = ((uint64_t)u << 32) | j;
-    }
-    const int64_t mine = lng ? 0 : cnt;
-    for (int64_t j = 0; j < mine; ++j) emit_task(e, true, u, b, du, s + (uint32_t)j, t0 + j);
-  }
-}
-
-__global__ void k_emit_long(EmitArgs e) {
-  if (*e.err) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const int64_t nl = (int64_t)*e.long_count;
-  for (int64_t r = wave; r < nl; r += nwave) {
-    const uint64_t sg = e.long_segs[r];
-    const int64_t u = (int64_t)(sg >> 32), j0 = (int64_t)(uint32_t)sg * EMIT_SEG;
-    const int64_t b = e.off[u], du = e.off[u + 1] - b, t0 = e.tpre[u];
-    const uint32_t s = e.ustart[u];
-    const int64_t cnt = min(du - s, j0 + EMIT_SEG);
-    for (int64_t i0 = j0; i0 < cnt; i0 += 64) {
-      const int64_t i = i0 + lane;
-      emit_task(e, i < cnt, u, b, du, s + (uint32_t)i, t0 + i);
-    }
-  }
 }
 
 // Hub list: the flagged tasks, compacted with one atomic per tile of HUB_TILE
@@ -355,13 +293,6 @@ __global__ void __launch_bounds__(256) k_hub_list(const uint64_t* __restrict__ t
     }
     __syncthreads();
   }
-}
-
-static void launch_emit(const EmitArgs& e, hipStream_t s) {
-  const int64_t waves_short = (e.n + 63) / 64;
-  const int blocks_short = (int)std::max<int64_t>(1, std::min<int64_t>((waves_short + 3) / 4, 65536));
-  k_emit_short<<<blocks_short, 256, 0, s>>>(e);
-  k_emit_long<<<16384, 256, 0, s>>>(e);
 }
 
 // Row of entry j: the last x in [lo, hi) with off[x] <= j, given off[lo] <= j
@@ -1562,7 +1493,7 @@ static size_t census_scratch_bound(int64_t n, int64_t nnz) {
     b += r(8 * ((n + SCAN_B - 1) / SCAN_B + 1));
   }
   if (m > 0) {
-    b += r(8 * m) + r(4 * m) + r(8 * m) + r(8 * m) + r(8 * (m + 1)) + r(8 * emit_seg_cap(n, m));
+    b += r(8 * m) + r(4 * m) + r(8 * m) + r(8 * m) + r(8 * (m + 1));
     b += r(8 * ((m + SCAN_B - 1) / SCAN_B + 1));
   }
   return b;
@@ -1661,10 +1592,8 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     ALLOC(hub_task, hub_cap);
     ALLOC(hub_nch, hub_cap);
     ALLOC(hub_pre, hub_cap + 1);
-    uint64_t* long_segs = nullptr;
-    ALLOC(long_segs, emit_seg_cap(n, ntasks));
-    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, 1, hub_thr, long_segs, acc + NC + 3, err};
-    launch_emit(e, s);
+    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, 1, hub_thr, err};
+    launch_emit_entries(e, nnz, s);
     // A schedule reorders the last batches of the queue: in place, or, with
     // per-task cycle recording, through a queue-position -> task index map
     // that keeps the tasks (and so the cycles) in CSR order.
@@ -1968,7 +1897,6 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   p->vbase = vbase;
   p->out = d_out;
   uint32_t *grow = nullptr, *ustart = nullptr, *packed = nullptr, *tskip = nullptr, *rowmark = nullptr;
-  uint64_t* long_segs = nullptr;
   int64_t *ntask = nullptr, *tpre = nullptr, *bsum = nullptr;
   uint64_t* tasks = nullptr;
   unsigned long long* q = nullptr;  // census queue [2], long rows, grouped bins [3]
@@ -1979,7 +1907,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 6) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
       plan_alloc(p, &ntask, nv) || plan_alloc(p, &tpre, nv + 1) || plan_alloc(p, &bsum, nv / SCAN_B + 2) ||
       plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks) || plan_alloc(p, &tskip, ntasks) ||
-      plan_alloc(p, &long_segs, emit_seg_cap(nv, ntasks)) || plan_alloc(p, &rowmark, (nnz >> 5) + 1) ||
+      plan_alloc(p, &rowmark, (nnz >> 5) + 1) ||
       (grouped && plan_alloc(p, &order4, ntasks))) {
     plan_free(p);
     (void)hipGetLastError();
@@ -2036,7 +1964,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
     if (ntasks > 0) {
       // the ids of N(v) below u are counted (the merge starts N(v) at u) when
       // the short tasks run grouped, where every merged entry weighs
-      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, grouped ? 1 : 0, -1, long_segs, q + 2, p->err};
+      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, grouped ? 1 : 0, -1, p->err};
       launch_emit_entries(ea, nnz, s);
       if (grouped) {
         GroupArgs ga{};

@@ -141,3 +141,28 @@ def test_training_beats_degree_heuristic(torch):
     mse = float(((costmodel.forward(w, X) - t) ** 2).mean().item())
     base = costmodel.affine_baseline_mse(X, t)
     assert mse < base, (mse, base)
+
+
+def test_trained_network_on_held_out_graphs(torch):
+    """Trained on the cycles of two R-MAT graphs, the network predicts the
+    per-task cycles of graphs it never saw (another R-MAT seed, a Chung-Lu
+    graph) better than the affine fit of log2(d(u)+d(v)) made on the same
+    training samples."""
+    Xs, ts = [], []
+    for g in (graphs.workload("rmat10"), graphs.rmat(15, 16, seed=2, recip_p=0.1)):
+        cyc = costmodel.record_cycles(g)
+        X = costmodel.features(g)
+        keep = cyc > 0
+        Xs.append(X[keep]); ts.append(torch.log2(cyc[keep].double()).float())
+    X, t = torch.cat(Xs).contiguous(), torch.cat(ts).contiguous()
+    w, hist = costmodel.train(X, t, epochs=25, batch=4096, lr=3e-3)
+    coef = costmodel.affine_fit(X, t)
+    for h in (graphs.rmat(14, 16, seed=9), graphs.chung_lu(1 << 14, 2.1, 16.0, 2048.0, seed=4)):
+        cyc = costmodel.record_cycles(h)
+        Xh = costmodel.features(h)
+        keep = cyc > 0
+        Xh, th = Xh[keep].contiguous(), torch.log2(cyc[keep].double()).float().contiguous()
+        net = costmodel.model_mse(w, Xh, th)
+        aff = costmodel.affine_mse(coef, Xh, th)
+        assert net < aff, (h.n, net, aff)
+

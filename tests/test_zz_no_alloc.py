@@ -29,12 +29,12 @@ def _scratch_bound(n, nnz):
     m = nnz // 2
     r = lambda b: (max(b, 1) + 255) // 256 * 256  # noqa: E731
     scan_b = 256 * 16
-    b = r(4) + r(160)
+    b = r(4) + r(21 * 8)
     if n > 0:
         b += r(4 * n) + r(8 * n) + r(8 * (n + 1)) + r(4 * ((nnz >> 5) + 1)) + r(4 * (nnz + 1024))
         b += r(8 * ((n + scan_b - 1) // scan_b + 1))
     if m > 0:
-        b += r(8 * m) + r(4 * m) + r(8 * m) + r(8 * m) + r(8 * (m + 1)) + r(8 * (n + m // 1024 + 1))
+        b += r(8 * m) + r(4 * m) + r(8 * m) + r(8 * m) + r(8 * (m + 1))
         b += r(8 * ((m + scan_b - 1) // scan_b + 1))
     return b
 
@@ -66,9 +66,9 @@ def test_noalloc_matches_allocating_entry(torch):
 
 
 def test_noalloc_near_the_limit(torch):
-    # R-MAT scale 17, edge factor 12: 63.6 MiB of the 64 MiB scratch
+    # R-MAT scale 17, edge factor 12: 62.6 MiB of the 64 MiB scratch
     g = graphs.rmat(17, 12, seed=2)
-    assert 0.99 * SCRATCH <= _scratch_bound(g.n, g.nnz) <= SCRATCH, _scratch_bound(g.n, g.nnz)
+    assert 0.97 * SCRATCH <= _scratch_bound(g.n, g.nnz) <= SCRATCH, _scratch_bound(g.n, g.nnz)
     want, got, _, _, _ = _both(torch, g)
     assert got == want
 
