@@ -314,6 +314,23 @@ int triad_mlp_train(float *d_w, const float *d_x, const float *d_t, int64_t m, i
 const char *triad_last_error(void);
 int triad_version(void);
 
+/* Memory cap (process-wide; 0 = none, the default): the device memory any one
+ * later call may allocate, counting its stream-ordered scratch, the input
+ * copies of triad_census / triad_census_ex and a batch plan's buffers (the
+ * no-allocation census allocates nothing and is not affected). A call that
+ * would go past the cap returns TRIAD_ENOMEM with nothing written to its
+ * outputs. bytes < 0: TRIAD_EINVAL. Needs no device. */
+int triad_set_memory_cap(int64_t bytes);
+
+/* Test hook for callers' error handling (not for production use): each of the
+ * next `count` single-graph census calls of the process (triad_census,
+ * triad_census_ex, triad_census_device, triad_census_device_noalloc,
+ * triad_labelled_census_device) that gets past input validation raises the
+ * device error flag after its census kernel, as a kernel that detected a
+ * fault would; such a call returns TRIAD_EDEVICE and writes no output. count =
+ * 0 cancels what is pending; count < 0: TRIAD_EINVAL. Needs no device. */
+int triad_test_inject_device_error(int32_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,9 @@ Functions (all plain C in ``liboracle.so``, wrapped with ctypes):
 * :func:`labelled_census` the 64-state census (states of triples a < b < c by
                         id order, Sec. 3), by the same sweep.
 * :func:`brute64`       the 64-state census by its definition, every triple.
+
+``oracle.checkpoint`` runs the census in chunks of CSR entries with a JSON
+checkpoint after each, so that a long run can stop and resume exactly.
 """
 from __future__ import annotations
 

@@ -1268,8 +1268,8 @@ __device__ __forceinline__ void add_common_neighbours(uint64_t* c) {
 }
 
 __global__ void k_finalize(const unsigned long long* __restrict__ acc, uint64_t clo, uint64_t chi,
-                           uint64_t* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+                           const uint32_t* __restrict__ err, uint64_t* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *err) return;  // an error writes no output
   uint64_t c[16];
   for (int k = 0; k < 16; ++k) c[k] = acc[k];
   add_common_neighbours(c);
@@ -1289,8 +1289,8 @@ __global__ void k_finalize(const unsigned long long* __restrict__ acc, uint64_t 
 // State 0 (no arc) = C(n,3) minus the rest, in two 64-bit words (out[64] is
 // the high word).
 __global__ void k_finalize_lab(const unsigned long long* __restrict__ acc, uint64_t clo, uint64_t chi,
-                               uint64_t* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+                               const uint32_t* __restrict__ err, uint64_t* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0 || *err) return;  // an error writes no output
   uint64_t c[64];
   for (int k = 0; k < 64; ++k) c[k] = acc[k];
   for (uint32_t st = 1; st < 64; ++st) {
@@ -1500,10 +1500,12 @@ static size_t census_scratch_bound(int64_t n, int64_t nnz) {
 }
 
 // The census of one device-resident graph. labelled: the 64-state census
-// (65 output words) instead of the 16 classes (17 words).
+// (65 output words) instead of the 16 classes (17 words). allocated_before:
+// device bytes the caller allocated for this call (counted against the
+// memory cap). Outputs are written only on success.
 int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr, const uint8_t* flg,
                   const triad_opts* opts, hipStream_t s, uint64_t* d_out, uint64_t* h_out, void* arena = nullptr,
-                  size_t arena_bytes = 0, bool labelled = false) {
+                  size_t arena_bytes = 0, bool labelled = false, size_t allocated_before = 0) {
   triad_opts o{};
   if (opts) o = *opts;
   const int NC = labelled ? 64 : 16;  // census counters
@@ -1535,7 +1537,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   }
   Events ev;
   if (o.timing) HIPCHK(ev.init());
-  Scratch scratch = arena ? Scratch(s, arena, arena_bytes) : Scratch(s);
+  Scratch scratch = arena ? Scratch(s, arena, arena_bytes) : Scratch(s, allocated_before);
   uint32_t* err = nullptr;
   // NC census counters, 2 queue counters, hub tasks, long rows, grouped-task claims
   unsigned long long* acc = nullptr;
@@ -1651,19 +1653,25 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     }
     HIPCHK(hipGetLastError());
   }
+  // test hook: the census reports a device fault through the error flag
+  if (take_injected_fault()) k_fill_u32<<<1, 64, 0, s>>>(err, 1, ERR_DEVICE);
   ev.rec(3, s);
   if (labelled)
-    k_finalize_lab<<<1, 64, 0, s>>>(acc, clo, chi, d_out);
+    k_finalize_lab<<<1, 64, 0, s>>>(acc, clo, chi, err, d_out);
   else
-    k_finalize<<<1, 64, 0, s>>>(acc, clo, chi, d_out);
+    k_finalize<<<1, 64, 0, s>>>(acc, clo, chi, err, d_out);
   HIPCHK(hipGetLastError());
   ev.rec(4, s);
-  if (h_out) HIPCHK(hipMemcpyAsync(h_out, d_out, (NC + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  uint64_t hi0 = 0;  // high word of the null count
-  HIPCHK(hipMemcpyAsync(&hi0, d_out + NC, sizeof hi0, hipMemcpyDeviceToHost, s));
+  // staged on the host: h_out is written only once the error flag is clear
+  uint64_t hres[65];
+  HIPCHK(hipMemcpyAsync(hres, d_out, (NC + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&errh, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (errh) return fail(status_from_bits(errh), "input validation failed on the device");
+  if (errh)
+    return fail(status_from_bits(errh), errh & ERR_DEVICE ? "the device reported a fault during the census"
+                                                          : "input validation failed on the device");
+  if (h_out) std::memcpy(h_out, hres, (NC + 1) * sizeof(uint64_t));
+  const uint64_t hi0 = hres[NC];  // high word of the null count
   if (o.timing) {
     o.timing->prep_ms = ev.ms(0, 1);
     o.timing->tasks_ms = ev.ms(1, 2);
@@ -1756,8 +1764,9 @@ __global__ void k_check_tasks(const int64_t* __restrict__ tpre, int64_t nv, int6
 }
 
 // Per graph: 003 = C(n_g, 3) minus the rest (n_g < 4,801,281 keeps C(n_g,3) < 2^64).
-__global__ void k_finalize_batch(int32_t G, const int64_t* __restrict__ vbase, unsigned long long* __restrict__ gout,
-                                 const uint32_t* __restrict__ err) {
+__global__ void k_finalize_batch(int32_t G, const int64_t* __restrict__ vbase,
+                                 const unsigned long long* __restrict__ gout, const uint32_t* __restrict__ err,
+                                 uint64_t* __restrict__ out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G || *err) return;
   const uint64_t n = (uint64_t)(vbase[g + 1] - vbase[g]);
@@ -1774,10 +1783,10 @@ __global__ void k_finalize_batch(int32_t G, const int64_t* __restrict__ vbase, u
   add_common_neighbours(c);
   uint64_t s = 0;
   for (int k = 1; k < 16; ++k) {
-    gout[16 * (uint64_t)g + k] = c[k];
+    out[16 * (uint64_t)g + k] = c[k];
     s += c[k];
   }
-  gout[16 * (uint64_t)g] = c3 - s;
+  out[16 * (uint64_t)g] = c3 - s;
 }
 
 // Content signature of a batch for the autotuner's cache: a sum of hashes of
@@ -1834,6 +1843,7 @@ struct triad_batch_plan {
   hipGraphExec_t exec = nullptr;
   hipStream_t last = nullptr;
   int launched = 0;
+  size_t bytes = 0;  // device memory the plan holds (counted against the memory cap)
 };
 
 namespace triad {
@@ -1848,8 +1858,13 @@ static void plan_free(triad_batch_plan* p) {
 
 template <class T>
 static hipError_t plan_alloc(triad_batch_plan* p, T** ptr, int64_t count) {
-  hipError_t e = hipMalloc((void**)ptr, (size_t)std::max<int64_t>(count, 1) * sizeof(T));
-  if (e == hipSuccess) p->bufs.push_back(*ptr);
+  const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  if (!within_cap(p->bytes + bytes)) return hipErrorOutOfMemory;
+  hipError_t e = hipMalloc((void**)ptr, bytes);
+  if (e == hipSuccess) {
+    p->bufs.push_back(*ptr);
+    p->bytes += bytes;
+  }
   return e;
 }
 
@@ -1904,7 +1919,8 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   // short tasks run grouped (task records hold 32-bit entry offsets)
   const bool grouped = ntasks > 0 && nnz + PAD < ((int64_t)1 << 32) && o.short_tasks >= 0;
   int64_t* order4 = nullptr;
-  if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 6) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
+  unsigned long long* gacc = nullptr;  // per-graph counters; d_out is written only by a clean finalize
+  if (plan_alloc(p, &p->err, 1) || plan_alloc(p, &q, 6) || plan_alloc(p, &gacc, (int64_t)G * 16) || plan_alloc(p, &grow, nv) || plan_alloc(p, &ustart, nv) ||
       plan_alloc(p, &ntask, nv) || plan_alloc(p, &tpre, nv + 1) || plan_alloc(p, &bsum, nv / SCAN_B + 2) ||
       plan_alloc(p, &packed, nnz + PAD) || plan_alloc(p, &tasks, ntasks) || plan_alloc(p, &tskip, ntasks) ||
       plan_alloc(p, &rowmark, (nnz >> 5) + 1) ||
@@ -1928,12 +1944,12 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   a.nhub = 0;
   a.chunk = 1;
   a.qctr = q;
-  a.acc = (unsigned long long*)d_out;
+  a.acc = gacc;
   a.cycles = nullptr;
   a.wave_span = nullptr;
   a.grow = grow;
   a.vbase = vbase;
-  a.gout = (unsigned long long*)d_out;
+  a.gout = gacc;
   a.err = p->err;
   a.cls = class_slices();
   const int groups = census_groups(waves, variant, 2, o.grid_groups);
@@ -1951,7 +1967,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
   s = cs;
   k_fill_u32<<<1, 64, 0, s>>>(p->err, 1, 0);
   k_fill_u64<<<1, 64, 0, s>>>((uint64_t*)q, 6, 0);  // queue counters, long rows, grouped bins
-  k_fill_u64<<<grid_for((int64_t)G * 16, 256, 4096), 256, 0, s>>>(d_out, (int64_t)G * 16, 0);
+  k_fill_u64<<<grid_for((int64_t)G * 16, 256, 4096), 256, 0, s>>>((uint64_t*)gacc, (int64_t)G * 16, 0);
   if (nv > 0) {
     k_fill_u32<<<grid_for((nnz >> 5) + 1, 256, 4096), 256, 0, s>>>(rowmark, (nnz >> 5) + 1, 0);
     k_rows_batch<<<grid_for(nv, 256, 65535), 256, 0, s>>>(G, nv, nnz, vbase, off, nbr, grow, ustart, ntask, rowmark,
@@ -1981,7 +1997,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
         ga.nlong = q + 4;
         ga.order4 = order4;
         ga.acc = nullptr;
-        ga.gout = (unsigned long long*)d_out;
+        ga.gout = gacc;
         ga.err = p->err;
         ga.cls = class_slices();
         k_census_grouped<true><<<group_grid<true>(), GROUP_WAVES * 64, 0, s>>>(ga);
@@ -1992,7 +2008,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
       (void)launch_census(waves, variant, a, groups, s);
     }
   }
-  k_finalize_batch<<<(G + 255) / 256, 256, 0, s>>>(G, vbase, (unsigned long long*)d_out, p->err);
+  k_finalize_batch<<<(G + 255) / 256, 256, 0, s>>>(G, vbase, gacc, p->err, d_out);
   e = hipStreamEndCapture(s, &p->graph);
   if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
   (void)hipStreamDestroy(cs);
@@ -2066,6 +2082,9 @@ int triad_census_ex(int64_t n, const int64_t* off, const int32_t* nbr, const uin
   const int64_t nnz = off[n];
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(TRIAD_EDEVICE, "no HIP device available");
+  const size_t in_bytes = sizeof(int64_t) * (n + 1) + sizeof(int32_t) * std::max<int64_t>(nnz, 1) +
+                          std::max<int64_t>((nnz + 3) / 4, 1) + 17 * sizeof(uint64_t);
+  if (!within_cap(in_bytes)) return fail(TRIAD_ENOMEM, "the input copy alone exceeds the memory cap");
   hipStream_t s;
   HIPCHK(hipStreamCreate(&s));
   int64_t* d_off = nullptr;
@@ -2097,7 +2116,7 @@ int triad_census_ex(int64_t n, const int64_t* off, const int32_t* nbr, const uin
   triad_opts o{};
   if (opts) o = *opts;
   o.validate = 0;  // checked on the host above
-  st = census_device(n, nnz, d_off, d_nbr, d_flg, &o, s, d_out, h);
+  st = census_device(n, nnz, d_off, d_nbr, d_flg, &o, s, d_out, h, nullptr, 0, false, in_bytes);
   if (st >= 0) {
     std::memcpy(out_u64, h, 16 * sizeof(uint64_t));
     if (out_003_hi) *out_003_hi = h[16];

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -12,6 +13,17 @@
 namespace triad {
 
 static thread_local std::string g_err;
+static std::atomic<int64_t> g_mem_cap{0};
+static std::atomic<int32_t> g_inject{0};
+
+int64_t memory_cap() { return g_mem_cap.load(std::memory_order_relaxed); }
+
+bool take_injected_fault() {
+  int32_t k = g_inject.load();
+  while (k > 0)
+    if (g_inject.compare_exchange_weak(k, k - 1)) return true;
+  return false;
+}
 
 void set_error(const std::string& msg) { g_err = msg; }
 int fail(int status, const std::string& msg) {
@@ -24,6 +36,7 @@ int status_from_bits(uint32_t bits) {
   if (bits & ERR_SELFLOOP) return TRIAD_ESELFLOOP;
   if (bits & ERR_UNSORTED) return TRIAD_EUNSORTED;
   if (bits & ERR_ASYM) return TRIAD_EASYM;
+  if (bits & ERR_DEVICE) return TRIAD_EDEVICE;
   return TRIAD_OK;
 }
 
@@ -141,6 +154,18 @@ extern "C" {
 
 const char* triad_last_error(void) { return g_err.c_str(); }
 int triad_version(void) { return TRIAD_ABI_VERSION; }
+
+int triad_set_memory_cap(int64_t bytes) {
+  if (bytes < 0) return fail(TRIAD_EINVAL, "memory cap must be >= 0");
+  g_mem_cap.store(bytes);
+  return TRIAD_OK;
+}
+
+int triad_test_inject_device_error(int32_t count) {
+  if (count < 0) return fail(TRIAD_EINVAL, "injected fault count must be >= 0");
+  g_inject.store(count);
+  return TRIAD_OK;
+}
 
 int triad_validate_host(int64_t n, const int64_t* off, const int32_t* nbr, const uint8_t* flg, int32_t level) {
   if (n < 0 || n >= ((int64_t)1 << 30)) return fail(TRIAD_EINVAL, "n must be in [0, 2^30)");

@@ -20,6 +20,7 @@ enum : uint32_t {
   ERR_SELFLOOP = 2u,  // a row lists its own vertex
   ERR_UNSORTED = 4u,  // a row not strictly increasing
   ERR_ASYM = 8u,      // missing mirror entry or flag not mirrored
+  ERR_DEVICE = 16u,   // a fault detected on the device (raised today only by the test hook)
 };
 
 int status_from_bits(uint32_t bits);
@@ -69,16 +70,30 @@ int device_info(DeviceInfo* out);
       return fail(TRIAD_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));     \
   } while (0)
 
+// Process-wide cap on the device memory one call may allocate (0 = none),
+// set by triad_set_memory_cap. within_cap(total) says whether a call that has
+// allocated `total` bytes so far stays within it.
+int64_t memory_cap();
+inline bool within_cap(size_t total) {
+  const int64_t c = memory_cap();
+  return c <= 0 || total <= (size_t)c;
+}
+// Test hook: true (once per injected fault) when the calling census should
+// raise ERR_DEVICE after its census kernel; set by triad_test_inject_device_error.
+bool take_injected_fault();
+
 // Scratch memory of one call. By default stream-ordered allocations, released
-// (in stream order) on destruction. Given an arena (a caller-owned device
-// range), it hands out 256-byte aligned pieces of it instead and allocates
-// nothing; a request past the arena's end fails.
+// (in stream order) on destruction; `total` counts what the call has
+// allocated (starting from what it allocated before this object existed) and
+// a request that would take it past the memory cap fails. Given an arena (a
+// caller-owned device range), it hands out 256-byte aligned pieces of it
+// instead and allocates nothing; a request past the arena's end fails.
 struct Scratch {
   hipStream_t s;
   std::vector<void*> ptrs;
   char* arena = nullptr;
-  size_t cap = 0, used = 0;
-  explicit Scratch(hipStream_t st) : s(st) {}
+  size_t cap = 0, used = 0, total = 0;
+  explicit Scratch(hipStream_t st, size_t allocated_before = 0) : s(st), total(allocated_before) {}
   Scratch(hipStream_t st, void* base, size_t bytes) : s(st), arena(static_cast<char*>(base)), cap(bytes) {}
   ~Scratch() {
     for (void* p : ptrs) (void)hipFreeAsync(p, s);
@@ -93,8 +108,12 @@ struct Scratch {
       used = at + bytes;
       return hipSuccess;
     }
+    if (!within_cap(total + bytes)) return hipErrorOutOfMemory;
     hipError_t e = hipMallocAsync((void**)p, bytes, s);
-    if (e == hipSuccess) ptrs.push_back(*p);
+    if (e == hipSuccess) {
+      ptrs.push_back(*p);
+      total += bytes;
+    }
     return e;
   }
 };

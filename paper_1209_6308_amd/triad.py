@@ -38,7 +38,8 @@ EXPORTS = [
     "triad_batch_plan_create", "triad_batch_plan_launch", "triad_batch_plan_status",
     "triad_batch_plan_destroy", "triad_census_batch", "triad_batch_autotune",
     "triad_csr_from_arcs", "triad_census_update", "triad_significance_profile", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
-    "triad_mlp_train", "triad_last_error", "triad_version",
+    "triad_mlp_train", "triad_last_error", "triad_version", "triad_set_memory_cap",
+    "triad_test_inject_device_error",
 ]
 
 
@@ -103,6 +104,8 @@ def lib():
             "triad_mlp_train": [vp, vp, vp, i64, i32, i32, ctypes.c_float, u64, vp, vp],
             "triad_last_error": [],
             "triad_version": [],
+            "triad_set_memory_cap": [i64],
+            "triad_test_inject_device_error": [i32],
         }
         for name, args in sigs.items():
             if hasattr(L, name):
@@ -166,6 +169,16 @@ def _result(out, hi):
     res = [int(x) for x in out[:16]]
     res[0] += int(hi) << 64
     return res
+
+
+def set_memory_cap(nbytes):
+    """Cap the device memory any one later call may allocate (0 = no cap)."""
+    return _check(lib().triad_set_memory_cap(int(nbytes)))
+
+
+def inject_device_error(count):
+    """Test hook: the next `count` single-graph census calls report a device fault."""
+    return _check(lib().triad_test_inject_device_error(int(count)))
 
 
 def triad_validate_host(n, offsets, nbrs, flags, level=0):

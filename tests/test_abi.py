@@ -95,6 +95,24 @@ def test_census_errors_before_device_use():
     assert "out of range" in triad.last_error()
 
 
+def test_failure_controls_on_the_host():
+    # the memory cap and the device-fault hook are host settings: bad values
+    # are rejected, good ones accepted, with no device involved
+    L = triad.lib()
+    assert L.triad_set_memory_cap(-1) == triad.EINVAL
+    assert "cap" in triad.last_error()
+    assert L.triad_set_memory_cap(1 << 20) == 0 and L.triad_set_memory_cap(0) == 0
+    assert L.triad_test_inject_device_error(-2) == triad.EINVAL
+    assert L.triad_test_inject_device_error(5) == 0 and L.triad_test_inject_device_error(0) == 0
+    # a cap does not change host-side validation
+    n, off, nb, fl = _valid()
+    triad.set_memory_cap(1)
+    try:
+        assert triad.triad_validate_host(n, off, nb, fl, 1) == 0
+    finally:
+        triad.set_memory_cap(0)
+
+
 def test_library_is_built_for_gfx950():
     path = _build.triad_lib_path()
     data = open(path, "rb").read()
