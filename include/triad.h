@@ -279,8 +279,10 @@ int triad_significance_profile(int32_t G, const uint64_t *d_ensemble, const uint
  * Cost model: an FP32 multilayer perceptron 6 -> 32 -> 32 -> 1 with ReLU
  * hidden layers. Parameters, packed in this order: W1[32][6], b1[32],
  * W2[32][32], b2[32], W3[32], b3 (1313 floats). Input features of a task
- * (u,v): log2(1+x) of d(u), d(v), d(u)+d(v), min, max, and the number of
- * entries of N(u) above v. Target: log2 of the task's measured cycles. */
+ * (u,v), from the lengths its merge walks: with a = the ids of N(u) above u
+ * and b = the ids of N(v) not below u, log2(1+x) of a, b, a+b, min(a,b),
+ * max(a,b), and the number of entries of N(u) above v. Target: log2 of the
+ * task's measured cycles. */
 #define TRIAD_MLP_IN 6
 #define TRIAD_MLP_HIDDEN 32
 #define TRIAD_MLP_PARAMS (TRIAD_MLP_HIDDEN * TRIAD_MLP_IN + TRIAD_MLP_HIDDEN + \

@@ -10,8 +10,11 @@ Loss: mean squared error L = (1/m) sum_s (y_s - t_s)^2; gradients by the
 chain rule, written out layer by layer (no autodiff library).
 Optimiser: Adam (Kingma and Ba, "Adam: A Method for Stochastic Optimization",
 ICLR 2015) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
-Features of a task (u, v), each log2(1 + x): d(u), d(v), d(u)+d(v),
-min(d(u), d(v)), max(d(u), d(v)), and the number of entries of N(u) above v.
+Features of a task (u, v), each log2(1 + x), from the lengths of the two
+lists its merge walks (the sweep of Fig. 5 needs, of N(u), only the ids above
+u, and of N(v) only the ids from u on, Sec. 6): a = |{w in N(u): w > u}|,
+b = |{w in N(v): w >= u}|, a + b, min(a, b), max(a, b), and the number of
+entries of N(u) above v.
 
 These are not census arithmetic: the census counts never depend on the model.
 Parity of the GPU kernels with this reference is to a floating-point
@@ -126,7 +129,11 @@ def task_features(offsets, nbrs):
     rows = np.repeat(np.arange(n, dtype=np.int64), d)
     j = np.flatnonzero(nb > rows)
     u, v = rows[j], nb[j]
-    du, dv = d[u], d[v]
+    # (row, id) pairs in CSR order are sorted, so a count of the ids of a row
+    # above (or from) a value is a difference of two sorted-search positions
+    key = rows * n + nb
+    a = off[u + 1] - np.searchsorted(key, u * n + u, side="right")  # ids of N(u) above u
+    b = off[v + 1] - np.searchsorted(key, v * n + u, side="left")   # ids of N(v) from u on
     above = off[u + 1] - j - 1
-    F = np.stack([du, dv, du + dv, np.minimum(du, dv), np.maximum(du, dv), above], axis=1).astype(np.float64)
+    F = np.stack([a, b, a + b, np.minimum(a, b), np.maximum(a, b), above], axis=1).astype(np.float64)
     return np.log2(1.0 + F)

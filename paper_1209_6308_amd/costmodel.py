@@ -3,8 +3,9 @@
 The model (an FP32 MLP 6 -> 32 -> 32 -> 1, see include/triad.h) is trained on
 the GPU by the library's own kernels (triad_mlp_train) on per-task cycle counts
 that the census kernel records (triad_opts.task_cycles), and then used by the
-census to bin and order the tasks (schedule="learned"). The d(u)+d(v)
-ordering (schedule="heuristic") is its fallback.
+census to bin and order the tasks (schedule="learned"). Ordering by the
+merge length d+(u) + d(v) - s(u, v) (schedule="heuristic": d+(u) the ids of
+N(u) above u, s the ids of N(v) below u) is its fallback.
 """
 from __future__ import annotations
 
@@ -106,7 +107,8 @@ def training_set(names=("rmat10", "rmat20"), max_samples=1 << 21, seed=3, device
 
 def affine_fit(X, t):
     """Least-squares coefficients (slope, intercept) of the best affine
-    predictor of log2 cycles from log2(1 + d(u) + d(v)), the heuristic's key."""
+    predictor of log2 cycles from log2(1 + merge length), the heuristic's key
+    (feature 2)."""
     x = X[:, 2].double().cpu().numpy()
     y = t.double().cpu().numpy()
     A = np.stack([x, np.ones_like(x)], axis=1)
@@ -122,7 +124,7 @@ def affine_mse(coef, X, t):
 
 def affine_baseline_mse(X, t):
     """Mean squared error of the best affine predictor of log2 cycles from
-    log2(1 + d(u) + d(v)) (the heuristic's key), fitted on the same samples."""
+    log2(1 + merge length) (the heuristic's key), fitted on the same samples."""
     return affine_mse(affine_fit(X, t), X, t)
 
 
@@ -142,7 +144,7 @@ def held_out_report(w, g, stream=None):
     X, t = X[keep].contiguous(), torch.log2(cyc[keep].double()).float().contiguous()
     out = {"graph": g.name, "tasks": int(X.shape[0]), "network_mse": model_mse(w, X, t, stream)}
     if e is not None and len(e) > 3:
-        out["affine_dudv_mse"] = affine_mse(e[3], X, t)
+        out["affine_len_mse"] = affine_mse(e[3], X, t)
     return out
 
 
@@ -162,4 +164,4 @@ def last_training_report(device="cuda", epochs=30):
     e = _CACHE.get((device, epochs))
     if e is None:
         return None
-    return {"final_mse": float(e[1][-1]), "affine_dudv_mse": e[2], "epochs": epochs}
+    return {"final_mse": float(e[1][-1]), "affine_len_mse": e[2], "epochs": epochs}

@@ -24,6 +24,9 @@ constexpr int NI = TRIAD_MLP_IN, NH = TRIAD_MLP_HIDDEN, NP = TRIAD_MLP_PARAMS;
 constexpr int OW1 = 0, OB1 = OW1 + NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH, OB3 = OW3 + NH;
 static_assert(OB3 + 1 == NP, "parameter layout");
 
+// Features of a task (u, v), from the lengths its merge really walks: a = the
+// ids of N(u) above u, b = the ids of N(v) from u on, and the ids of N(u)
+// above v (the part whose third vertices the task may count).
 __device__ __forceinline__ void task_features(uint32_t du, uint32_t dv, uint32_t above, float x[NI]) {
   const uint32_t mn = du < dv ? du : dv, mx = du < dv ? dv : du;
   x[0] = log2f(1.0f + (float)du);
@@ -73,13 +76,19 @@ __global__ void k_features_csr(int64_t n, const int64_t* __restrict__ off, const
     const uint32_t du = (uint32_t)(off[u + 1] - b);
     const int64_t t0 = tpre[u];
     const uint32_t cnt = (uint32_t)(tpre[u + 1] - t0);
-    const uint32_t s = du - cnt;  // first entry above u
+    const uint32_t s = du - cnt;  // first entry above u; cnt = d+(u), the ids above u
     for (uint32_t i = lane; i < cnt; i += 64) {
       const uint32_t k = s + i;
       const int32_t v = nbr[b + k];
-      const uint32_t dv = (uint32_t)(off[v + 1] - off[v]);
+      // ids of N(v) below u: lower bound of u in the row of v
+      int64_t lo = off[v], hi = off[v + 1];
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (nbr[mid] < (int32_t)u) lo = mid + 1; else hi = mid;
+      }
+      const uint32_t dv = (uint32_t)(off[v + 1] - lo);
       float x[NI];
-      task_features(du, dv, du - k - 1, x);
+      task_features(cnt, dv, du - k - 1, x);
       float* o = feat + (t0 + i) * NI;
       for (int q = 0; q < NI; ++q) o[q] = x[q];
     }
@@ -232,8 +241,10 @@ __global__ void k_zero_f32(float* p, int64_t m) {
 // keeps that order for the bulk of the queue and orders only its last batches
 // costliest first (longest processing time first), so that no costly batch is
 // claimed when the other wavefronts are about to run dry. Batch key: the sum
-// over its tasks of d(u)+d(v) + SCHED_TASK_OH (heuristic) or of the network's
-// predicted cycles (learned); tasks merged from the hub list add nothing. The
+// over its tasks of the merge length d+(u) + d(v) - s(u, v) + SCHED_TASK_OH
+// (heuristic; d+(u) the ids of N(u) above u, s the ids of N(v) below u) or of
+// the network's predicted cycles (learned); tasks merged from the hub list add
+// nothing. The
 // order is a stable counting sort over SCHED_BPO bins per octave of the key,
 // the first bin the costliest.
 constexpr float SCHED_BPO = 4.0f;
@@ -246,9 +257,9 @@ constexpr int64_t SCHED_CHUNK = 256;
 // ones claimed (about one per wavefront) costly enough to delay the whole
 // census: one of the last SCHED_TAIL_LAST predicted to cost more than the
 // mean of the last SCHED_TAIL_SAMPLE by SCHED_TAIL_SHARE / 10,000 of one
-// wavefront's share of the census. The share is the total of d(u)+d(v)+256
+// wavefront's share of the census. The share is the total of d+(u)+d(v)+256
 // over all tasks, per wavefront, converted to the key's units by the ratio of
-// the two sums over the sample. Only the sample is keyed first; the rest of
+// the key sum to the sum of d+(u)+d(v)+256 over the sample. Only the sample is keyed first; the rest of
 // the stretch is keyed and the stretch reordered only when the test says so.
 // Otherwise the queue keeps its CSR order, and with it the reuse of N(u)
 // across batches.
@@ -269,7 +280,7 @@ __device__ __forceinline__ float wave_sum_f32(float x) {
 
 // Bin of batches from .. nbatch-1 (bin[b - from]), one wavefront per batch
 // and one lane per task; with kval given, also the batch's key sum and its
-// sum of d(u)+d(v)+SCHED_TASK_OH (lval). Under the learned key every lane
+// sum of d+(u)+d(v)+SCHED_TASK_OH (lval). Under the learned key every lane
 // evaluates the network; the weights are read at wave-uniform addresses,
 // through the scalar cache.
 __global__ void __launch_bounds__(256) k_batch_keys(int mode, const float* __restrict__ gw,
@@ -277,6 +288,8 @@ __global__ void __launch_bounds__(256) k_batch_keys(int mode, const float* __res
                                                     const uint64_t* __restrict__ tasks, int64_t ntasks, int64_t from,
                                                     int64_t nbatch, uint8_t* __restrict__ bin,
                                                     float* __restrict__ kval, float* __restrict__ lval,
+                                                    const uint32_t* __restrict__ ustart,
+                                                    const uint32_t* __restrict__ tskip,
                                                     const uint32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
@@ -284,25 +297,27 @@ __global__ void __launch_bounds__(256) k_batch_keys(int mode, const float* __res
   const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t bt = from + wave; bt < nbatch; bt += nwave) {
     const int64_t t = bt * BATCH + lane;
-    uint32_t du = 0, dv = 0, above = 0;
+    uint32_t dp = 0, dv = 0, sv = 0, above = 0;
     bool live = false;
     if (t < ntasks) {
       const uint64_t tk = tasks[t];
       if (!(tk & HUB_BIT)) {
         const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu, k = (uint32_t)tk;
         const int64_t au = off[u];
-        du = (uint32_t)(off[u + 1] - au);
+        const uint32_t du = (uint32_t)(off[u + 1] - au);
+        dp = du - ustart[u];
         const uint32_t v = packed[au + k] >> 2;
         dv = (uint32_t)(off[v + 1] - off[v]);
+        sv = tskip[t];
         above = du - k - 1;
         live = true;
       }
     }
-    const float len = (float)du + (float)dv + SCHED_TASK_OH;
-    float c = len;
+    const float len = (float)dp + (float)dv + SCHED_TASK_OH;
+    float c = len - (float)sv;
     if (mode == 2) {
       float x[NI];
-      task_features(du, dv, above, x);
+      task_features(dp, dv - sv, above, x);
       c = exp2f(mlp_forward(gw, x));
     }
     const float sum = wave_sum_f32(live ? c : 0.0f);
@@ -550,14 +565,14 @@ int schedule_tail(int mode, const float* model, int64_t n, const int64_t* off, c
   ALLOC(part, NPARTS);
   hipLaunchKernelGGL(k_list_sums, dim3(NPARTS), dim3(256), 0, s, n, off, ustart, part);
   hipLaunchKernelGGL(k_batch_keys, dim3(grid_of(ns, 4, 65536)), dim3(256), 0, s, mode, model, off, packed,
-                     (const uint64_t*)tasks, ntasks, nfull - ns, nfull, bin + (tail - ns), kval, lval,
-                     (const uint32_t*)nullptr);
+                     (const uint64_t*)tasks, ntasks, nfull - ns, nfull, bin + (tail - ns), kval, lval, ustart,
+                     (const uint32_t*)tskip, (const uint32_t*)nullptr);
   hipLaunchKernelGGL(k_tail_decide, dim3(1), dim3(256), 0, s, (const float*)kval, (const float*)lval, ns,
                      SCHED_TAIL_LAST, (const unsigned long long*)part, NPARTS, ntasks, nwaves, share, skip);
   if (tail > ns)
     hipLaunchKernelGGL(k_batch_keys, dim3(grid_of(tail - ns, 4, 65536)), dim3(256), 0, s, mode, model, off, packed,
                        (const uint64_t*)tasks, ntasks, from, nfull - ns, bin, (float*)nullptr, (float*)nullptr,
-                       (const uint32_t*)skip);
+                       ustart, (const uint32_t*)tskip, (const uint32_t*)skip);
   if (int st = stable_bin_order(bin, tail, SCHED_CHUNK, from, border, skip, scratch, s)) return st;
   // the task words move together with their N(v) skip counts
   uint64_t* tmp = nullptr;

@@ -128,7 +128,7 @@ def test_wave_spans(torch):
 
 def test_training_beats_degree_heuristic(torch):
     """What the trained network gains: a lower prediction error of per-task
-    log2 cycles than the best affine fit of log2(d(u)+d(v)), the heuristic's key."""
+    log2 cycles than the best affine fit of log2(merge length), the heuristic's key."""
     Xs, ts = [], []
     for g in (graphs.workload("rmat10"), graphs.rmat(15, 16, seed=2, recip_p=0.1)):
         cyc = costmodel.record_cycles(g)
@@ -146,7 +146,7 @@ def test_training_beats_degree_heuristic(torch):
 def test_trained_network_on_held_out_graphs(torch):
     """Trained on the cycles of two R-MAT graphs, the network predicts the
     per-task cycles of graphs it never saw (another R-MAT seed, a Chung-Lu
-    graph) better than the affine fit of log2(d(u)+d(v)) made on the same
+    graph) better than the affine fit of log2(merge length) made on the same
     training samples."""
     Xs, ts = [], []
     for g in (graphs.workload("rmat10"), graphs.rmat(15, 16, seed=2, recip_p=0.1)):

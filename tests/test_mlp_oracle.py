@@ -59,8 +59,10 @@ def test_task_features_by_hand():
     off = [0, 3, 5, 7, 8]
     nb = [1, 2, 3, 0, 2, 0, 1, 0]
     F = mlp.task_features(off, nb)
-    # tasks in CSR order: (0,1), (0,2), (0,3), (1,2)
-    raw = np.array([[3, 2, 5, 2, 3, 2], [3, 2, 5, 2, 3, 1], [3, 1, 4, 1, 3, 0], [2, 2, 4, 2, 2, 0]], float)
+    # tasks in CSR order: (0,1), (0,2), (0,3), (1,2). Of N(u) the merge walks
+    # the ids above u (row 0: 1,2,3; row 1: 2), of N(v) the ids from u on
+    # (N(1) from 0: 0,2; N(2) from 0: 0,1; N(3) from 0: 0; N(2) from 1: 1)
+    raw = np.array([[3, 2, 5, 2, 3, 2], [3, 2, 5, 2, 3, 1], [3, 1, 4, 1, 3, 0], [1, 1, 2, 1, 1, 0]], float)
     assert np.allclose(F, np.log2(1 + raw))
 
 
