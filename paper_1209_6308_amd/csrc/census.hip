@@ -255,6 +255,7 @@ __device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int64_t u
 constexpr int HUB_TILE = 256 * 16;
 __global__ void __launch_bounds__(256) k_hub_list(const uint64_t* __restrict__ tasks, int64_t ntasks,
                                                   const int64_t* __restrict__ off, const uint32_t* __restrict__ packed,
+                                                  const uint32_t* __restrict__ ustart, const uint32_t* __restrict__ tskip,
                                                   int64_t chunk, uint64_t* __restrict__ hub_task,
                                                   int64_t* __restrict__ hub_nch, unsigned long long* __restrict__ hub_count,
                                                   const uint32_t* __restrict__ err) {
@@ -286,8 +287,10 @@ __global__ void __launch_bounds__(256) k_hub_list(const uint64_t* __restrict__ t
         const uint32_t u = (uint32_t)(tk >> 32) & 0x3FFFFFFFu, k = (uint32_t)tk;
         const int64_t au = off[u], du = off[u + 1] - au;
         const uint32_t v = packed[au + k] >> 2;
+        // the merged length: N(u) above u and N(v) from u on
+        const int64_t len = (du - ustart[u]) + (off[v + 1] - off[v]) - tskip[t];
         hub_task[h] = (uint64_t)t;
-        hub_nch[h] = (du + (off[v + 1] - off[v]) + chunk - 1) / chunk;
+        hub_nch[h] = (len + chunk - 1) / chunk;
       }
       slot += (uint64_t)__popcll(m);
     }
@@ -418,10 +421,10 @@ __device__ uint32_t global_split(const uint32_t* A, uint32_t la, const uint32_t*
 // One batch of work items, one item per lane (lane < cnt). An item merges
 // A = packed[aoff .. aoff+la) (a range of N(u)) with B = packed[boff ..
 // boff+lb) (a range of N(v)). A starts at the first id of N(u) above u and,
-// for a whole task, B at u: an id w < u is never counted (Fig. 5 step
-// 2.1.4), and the intersection sizes that complete the dyadic counts follow
-// from the triangle classes (k_finalize), so the ids below u are not needed.
-// (Chunks of split tasks keep all of N(v).)
+// B at u: an id w < u is never counted (Fig. 5 step 2.1.4), and the
+// intersection sizes that complete the dyadic counts follow from the triangle
+// classes (k_finalize), so the ids below u are not needed. A split task's
+// chunks divide that same trimmed merge.
 // uf = u | kind << 30 with kind 0 = a later chunk of a split task, 1 = its
 // first chunk, 2 = a whole task; the first two kinds also add their task's
 // dyadic term dyad = n - d(u) - d(v) (Fig. 5 step 2.1.3). vf = v << 2 | f_uv.
@@ -524,14 +527,14 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
         const uint32_t pv = g.packed[au0 + (uint32_t)tk];
         const int64_t bv0 = g.off[pv >> 2];
         const uint32_t dv = (uint32_t)(g.off[(pv >> 2) + 1] - bv0);
-        // the ids of N(u) above u
-        const uint32_t su = g.ustart[u];
-        const int64_t au = au0 + su, bv = bv0;
-        const uint32_t dla = du - su, dlb = dv;
+        // the ids of N(u) above u and of N(v) from u on
+        const uint32_t su = g.ustart[u], sv = min(g.tskip[bt.tid], dv);
+        const int64_t au = au0 + su, bv = bv0 + sv;
+        const uint32_t dla = du - su, dlb = dv - sv;
         const uint32_t* Ag = g.packed + au;
         const uint32_t* Bg = g.packed + bv;
         const uint64_t Ltot = (uint64_t)dla + dlb;
-        // the chunk count came from d(u) + d(v): trailing chunks may be empty
+        // the chunks split the merged length (a trailing chunk may be empty)
         const uint64_t d0 = min((uint64_t)c * g.chunk, Ltot), d1 = min(d0 + (uint64_t)g.chunk, Ltot);
         const uint32_t i0 = global_split(Ag, dla, Bg, dlb, (uint32_t)d0);
         const uint32_t i1 = global_split(Ag, dla, Bg, dlb, (uint32_t)d1);
@@ -555,7 +558,7 @@ __device__ bool fetch_batch(const CensusArgs& g, int lane, int& phase, Batch& bt
         if constexpr (LAB) {
           if (c == 0) {
             const uint32_t vv = pv >> 2;
-            lab_dyads(bt, g.n, u, vv, du, (int64_t)(uint32_t)tk, su, min(g.tskip[bt.tid], dv), dv, g.ustart[vv]);
+            lab_dyads(bt, g.n, u, vv, du, (int64_t)(uint32_t)tk, su, sv, dv, g.ustart[vv]);
           }
         }
       } else {
@@ -723,6 +726,35 @@ __device__ __forceinline__ void merge_round(WaveLds<W, HH, NC>& L, uint32_t na, 
   }
 }
 
+// Deferred counts of the long window of lopsided rounds whose ids are all
+// counted as found in one list only: such an id's class depends only on its
+// flag and on the round's class row (uniform), so each lane counts flags 1..3
+// in bytes 1..3 of one register (1 << 8f: a shift and a shift-add per id, no
+// LDS atomic), and the counts go to the LDS counters when the class row
+// changes, after pack_rounds<W>() rounds (a byte then holds at most that many
+// times W / 64 ids, below 256), and before every flush.
+struct FlagPack {
+  uint32_t acc;     // per lane: byte f = ids of flag f counted since the drain
+  uint32_t tbl;     // the class row those counts belong to (uniform)
+  uint32_t rounds;  // rounds counted since the drain (uniform)
+};
+template <int W>
+constexpr uint32_t pack_rounds() {
+  return 255u / (uint32_t)(W / 64);
+}
+
+template <int W, bool HH, int NC>
+__device__ __forceinline__ void pack_drain(WaveLds<W, HH, NC>& L, FlagPack& p, uint32_t col) {
+  static_assert(pack_rounds<W>() * (W / 64) < 256, "a byte counter would overflow");
+  constexpr uint32_t C = WaveLds<W, HH, NC>::COLS;
+  if (p.rounds == 0) return;
+  uint32_t* const hcol = L.hist + col;
+#pragma unroll
+  for (uint32_t f = 1; f < 4; ++f) atomicAdd(hcol + ((p.tbl >> (4 * f)) & 15u) * C, (p.acc >> (8 * f)) & 255u);
+  p.acc = 0;
+  p.rounds = 0;
+}
+
 // A round in which one window holds few ids (S, ns of them) and the other many
 // (G, ng): the same classification as the walk, entry by entry instead of in
 // merged order. Each id of S finds its match in G by a branchless lower-bound
@@ -733,7 +765,7 @@ __device__ __forceinline__ void merge_round(WaveLds<W, HH, NC>& L, uint32_t na, 
 template <int W, bool HH, int NC>
 __device__ __forceinline__ void lopsided_round(WaveLds<W, HH, NC>& L, uint32_t na, uint32_t nb, uint32_t uq,
                                                    uint32_t vq, uint64_t slice, uint32_t ga, uint32_t gb, uint32_t fuv,
-                                                   const LabTables& lt, uint32_t col, int lane) {
+                                                   const LabTables& lt, uint32_t col, int lane, FlagPack& pk) {
   constexpr uint32_t C = WaveLds<W, HH, NC>::COLS;
   constexpr bool LAB = NC == 64;
   const bool sA = na <= nb;  // the short window is N(u)'s
@@ -819,8 +851,15 @@ __device__ __forceinline__ void lopsided_round(WaveLds<W, HH, NC>& L, uint32_t n
 #pragma unroll
     for (int j = 0; j < W / 64; ++j) y[j] = G[j * 64 + lane];
     if (gfirst > thrG) {
+      if (pk.tbl != rowtbl || pk.rounds >= pack_rounds<W>()) {
+        pack_drain(L, pk, col);
+        pk.tbl = rowtbl;
+      }
+      uint32_t acc = pk.acc;
 #pragma unroll
-      for (int j = 0; j < W / 64; ++j) atomicAdd(hcol + __builtin_amdgcn_ubfe(rowtbl, y[j] << 2, 4) * C, 1u);
+      for (int j = 0; j < W / 64; ++j) acc += 1u << ((y[j] << 3) & 31u);  // byte f of the id's flag f
+      pk.acc = acc;
+      pk.rounds += 1;
     } else {
 #pragma unroll
       for (int j = 0; j < W / 64; ++j) {
@@ -904,6 +943,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   uint64_t t_start = CYC ? __builtin_amdgcn_s_memtime() : 0;
   uint32_t ra[W / 64], rb[W / 64];
   uint32_t na_ld = 0, nb_ld = 0;
+  FlagPack pk{0u, 0u, 0u};
 
   for (;;) {
     // ---- stage the loaded round in LDS (slots past the window get zeros or
@@ -971,6 +1011,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
     // ---- merge this round from LDS
     if (BAT && cur.gid != wg && cur.la + cur.lb > 0) {
       if (wg != 0xFFFFFFFFu) {
+        pack_drain(L, pk, col);
         flush_wave(L, lane, g.gout + 16 * (uint64_t)wg);
         steps = 0;
       }
@@ -978,7 +1019,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
     }
     if (min(na, nb) <= LOP_S && max(na, nb) >= LOP_G)
       lopsided_round<W, HH, NC>(L, na, nb, cur.uq, cur.vq, cur.slice, g.cls.ga[cur.f], g.cls.gb[cur.f], cur.f, g.lab,
-                                col, lane);
+                                col, lane, pk);
     else
       merge_round<W, HH, NC>(L, na, nb, cur.uq, cur.vq, cur.slice, cur.f, col, lane);
     steps += (na + nb) / (HH ? 16 : 32) + 4;
@@ -989,6 +1030,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
         t_start = t_end;
       }
       if (steps > (1u << 30)) {
+        pack_drain(L, pk, col);
         flush_wave(L, lane, BAT ? g.gout + 16 * (uint64_t)wg : g.acc);
         steps = 0;
       }
@@ -1003,6 +1045,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   }
   unsigned long long* tgt = g.acc;
   if (BAT) tgt = wg != 0xFFFFFFFFu ? g.gout + 16 * (uint64_t)wg : nullptr;
+  pack_drain(L, pk, col);
   if (tgt) flush_wave(L, lane, tgt);
   if (lane == 0 && g.wave_span) g.wave_span[2 * wave_id + 1] = __builtin_amdgcn_s_memrealtime();
 }
@@ -1607,8 +1650,8 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
         return st;
     }
     if (hub_thr >= 0)
-      k_hub_list<<<grid_for(ntasks, HUB_TILE, 32768), 256, 0, s>>>(tasks, ntasks, off, packed, chunk, hub_task, hub_nch,
-                                                                   acc + NC + 2, err);
+      k_hub_list<<<grid_for(ntasks, HUB_TILE, 32768), 256, 0, s>>>(tasks, ntasks, off, packed, ustart, tskip, chunk,
+                                                                   hub_task, hub_nch, acc + NC + 2, err);
     HIPCHK(hipGetLastError());
     if (hub_thr >= 0) {
       unsigned long long hc = 0;
