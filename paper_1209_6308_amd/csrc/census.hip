@@ -661,6 +661,12 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t* x, uint32_t n, uint
   // live across the round loop would be spilled
   uint32_t l = (uint32_t)lane;
   asm volatile("" : "+v"(l));
+  if (n <= 64) {
+    // a window of at most 64 ids (the short list of most lopsided rounds):
+    // one read and one compare per lane
+    const uint32_t v = key_of(x[min(l, n - 1)]);
+    return (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(l < n) & __builtin_amdgcn_ballot_w64(v <= bound));
+  }
   const uint32_t last = key_of(x[min(l * S + S - 1, n - 1)]);
   // (each ballot of one compare is that compare's lane mask as it stands;
   // masks are combined on the scalar unit)
