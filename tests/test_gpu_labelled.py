@@ -76,14 +76,16 @@ def test_schedules_and_wrapped_state0(torch):
     assert st == triad.OK_003_WRAPPED
 
 
-def test_rmat20_condensed_golden(torch):
-    """Full size: R-MAT scale 20; the condensed labelled census equals the
-    oracle's stored 16-class census of the same graph."""
-    path = os.path.join(GOLDEN, "census_rmat20.json")
+@pytest.mark.parametrize("name", ["rmat20", "rmat24"])
+def test_condensed_golden(torch, name):
+    """Full size: R-MAT scales 20 and 24 (the benchmark workload, 003 above
+    2^64); the condensed labelled census equals the oracle's stored 16-class
+    census of the same graph."""
+    path = os.path.join(GOLDEN, f"census_{name}.json")
     if not os.path.exists(path):
         pytest.skip("golden not generated")
     rec = json.load(open(path))
-    g = graphs.workload("rmat20")
+    g = graphs.workload(name)
     assert g.content_hash() == rec["content_hash"]
     lab, _, _ = _lab(g)
     lut = oracle.lut()

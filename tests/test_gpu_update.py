@@ -128,3 +128,54 @@ def test_update_errors(torch):
         with pytest.raises(triad.TriadError) as e:
             triad.census_update(g.n, g.nnz, *dev, c, *t)
         assert e.value.status == status
+
+
+def test_rmat24_batch_and_its_inverse(torch):
+    """Full size (R-MAT scale 24, the benchmark workload): a batch of 100,000
+    updates, each touching a different arc (deletions of present arcs,
+    insertions of absent ones), gives the census a full census of the
+    resulting CSR gives; the inverse batch (every deletion re-inserted, every
+    insertion deleted) from there returns the oracle's stored census and the
+    original CSR, byte for byte."""
+    import json
+    import os
+
+    from _helpers import GOLDEN
+    path = os.path.join(GOLDEN, "census_rmat24.json")
+    if not os.path.exists(path):
+        pytest.skip("golden not generated")
+    rec = json.load(open(path))
+    g = graphs.workload("rmat24")
+    assert g.content_hash() == rec["content_hash"]
+    want = [int(x) for x in rec["census"]]
+    off, nbr, flg = triad.to_device(g)
+    n, nnz, k = g.n, g.nnz, 100000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    # arcs of the graph as sorted keys row * n + col (an entry with bit0 set is the arc row -> col)
+    rows = torch.repeat_interleave(torch.arange(n, device="cuda"), off[1:] - off[:-1])
+    j = torch.arange(nnz, device="cuda")
+    f = (flg[j >> 2].to(torch.int64) >> (2 * (j & 3))) & 3
+    akey = (rows * n + nbr.to(torch.int64))[(f & 1) != 0]
+    del rows, j, f
+    dkey = torch.unique(akey[torch.randint(0, akey.numel(), (k // 2,), device="cuda", generator=gen)])
+    a = torch.randint(0, n, (k,), device="cuda", generator=gen)
+    b = (a + torch.randint(1, n, (k,), device="cuda", generator=gen)) % n
+    ikey = torch.unique(a * n + b)
+    pos = torch.searchsorted(akey, ikey).clamp(max=akey.numel() - 1)
+    ikey = ikey[akey[pos] != ikey][: k - dkey.numel()]
+    del akey
+    keys = torch.cat([dkey, ikey])
+    ins = torch.cat([torch.zeros(dkey.numel(), dtype=torch.uint8, device="cuda"),
+                     torch.ones(ikey.numel(), dtype=torch.uint8, device="cuda")])
+    perm = torch.randperm(keys.numel(), device="cuda", generator=gen)
+    keys, ins = keys[perm], ins[perm].contiguous()
+    us, ud = (keys // n).to(torch.int32).contiguous(), (keys % n).to(torch.int32).contiguous()
+    c1, csr1, chg = triad.census_update(n, nnz, off, nbr, flg, want, us, ud, ins)
+    assert chg > 0.9 * keys.numel()
+    nnz1 = int(csr1[1].numel())
+    full, st, _ = triad.triad_census_device(n, nnz1, *csr1, validate=1)
+    assert c1 == full
+    c2, csr2, _ = triad.census_update(n, nnz1, *csr1, c1, us, ud, (1 - ins).contiguous())
+    assert c2 == want
+    assert torch.equal(csr2[0], off) and torch.equal(csr2[1], nbr) and torch.equal(csr2[2], flg)
