@@ -391,10 +391,29 @@ template <int W, bool HH, int NC = 16>
 struct WaveLds {
   static constexpr int COLS = HH ? 32 : 64;
   static constexpr int NCLS = NC;
+  // the labelled census keeps two 16-bit counters per word (states 2r and
+  // 2r + 1 in row r), halving its counter array
+  static constexpr int ROWS = NC == 64 ? NC / 2 : NC;
   uint32_t a[W + 1];
   uint32_t b[W + 1];
-  uint32_t hist[NC * COLS];  // [class or state][column]
+  uint32_t hist[ROWS * COLS];  // [class or state row][column]
 };
+
+// Adds d (which may be negative, as two's complement) to counter k of a
+// lane's column hcol: one word per class, or half a word per labelled state.
+template <int W, bool HH, int NC>
+__device__ __forceinline__ void hist_add(uint32_t* hcol, uint32_t k, uint32_t d) {
+  constexpr uint32_t C = WaveLds<W, HH, NC>::COLS;
+  if constexpr (NC == 64)
+    atomicAdd(hcol + (k >> 1) * C, d << ((k & 1u) << 4));
+  else
+    atomicAdd(hcol + k * C, d);
+}
+
+// Labelled counters are flushed before any 16-bit field can leave +-32767:
+// a round changes a field by less than its share of `steps`, and the check
+// runs every round.
+constexpr uint32_t LAB_FLUSH_STEPS = 1u << 14;
 
 // Labelled census (64 states of a triple a < b < c by id order, Sec. 3): the
 // state of the triple of task (u, v) and a counted third vertex w, from the
@@ -725,7 +744,7 @@ __device__ __forceinline__ void merge_round(WaveLds<W, HH, NC>& L, uint32_t na, 
       const uint32_t sh = (((sb << 2) | fa) << 2) & 63u;  // the id bits of b shift out
       cls = (uint32_t)(slice >> sh) & 15u;
     }
-    atomicAdd(hcol + cls * WaveLds<W, HH, NC>::COLS, 1u);
+    hist_add<W, HH, NC>(hcol, cls, 1u);
     i += (uint32_t)ta;
     k += (uint32_t)tb;
     pos = i + k;
@@ -753,7 +772,7 @@ template <int W, bool HH, int NC>
 __device__ __forceinline__ void pack_drain(WaveLds<W, HH, NC>& L, FlagPack& p, uint32_t col) {
   static_assert(pack_rounds<W>() * (W / 64) < 256, "a byte counter would overflow");
   constexpr uint32_t C = WaveLds<W, HH, NC>::COLS;
-  if (p.rounds == 0) return;
+  if (NC == 64 || p.rounds == 0) return;  // (the labelled census never packs)
   uint32_t* const hcol = L.hist + col;
 #pragma unroll
   for (uint32_t f = 1; f < 4; ++f) atomicAdd(hcol + ((p.tbl >> (4 * f)) & 15u) * C, (p.acc >> (8 * f)) & 255u);
@@ -828,9 +847,9 @@ __device__ __forceinline__ void lopsided_round(WaveLds<W, HH, NC>& L, uint32_t n
       cls = counted ? (uint32_t)(slice >> (idx << 2)) & 15u : 0u;
       gcls = (common & (kx > thrG)) ? (rowtbl >> (4u * fg)) & 15u : 0u;
     }
-    atomicAdd(hcol + cls * C, 1u);
+    hist_add<W, HH, NC>(hcol, cls, 1u);
     // the matched G id is counted below as found in G only: take that back
-    if (common) atomicSub(hcol + gcls * C, 1u);
+    if (common) hist_add<W, HH, NC>(hcol, gcls, ~0u);
   }
   if constexpr (LAB) {
     // ids of G as found in G only: N(v) only (sA) counts above u, its state
@@ -840,7 +859,7 @@ __device__ __forceinline__ void lopsided_round(WaveLds<W, HH, NC>& L, uint32_t n
     for (uint32_t e = (uint32_t)lane; e - (uint32_t)lane < ng; e += 64) {
       const uint32_t y = G[e < ng ? e : 0];
       const uint32_t off = ((e < ng) & (y > thrG)) ? y << 3 : 0u;
-      atomicAdd(hcol + __builtin_amdgcn_ubfe(y > vq ? thi : tlo, off, 6) * C, 1u);
+      hist_add<W, HH, NC>(hcol, __builtin_amdgcn_ubfe(y > vq ? thi : tlo, off, 6), 1u);
     }
     return;
   }
@@ -891,14 +910,27 @@ template <int W, bool HH, int NC>
 __device__ void flush_wave(WaveLds<W, HH, NC>& L, int lane, unsigned long long* acc) {
   constexpr int C = WaveLds<W, HH, NC>::COLS;
   wave_lds_sync();
-  for (int c = 1; c < NC; ++c) {
-    // columns are signed: a lopsided round may take a count back from a column
-    // other than the one that received it
-    const uint64_t x = lane < C ? (uint64_t)(int64_t)(int32_t)L.hist[c * C + lane] : 0u;
-    const uint64_t sum = wave_sum64(x);
-    if (lane == 0 && sum) atomicAdd(&acc[c], (unsigned long long)sum);
+  // counters are signed: a lopsided round may take a count back from a column
+  // other than the one that received it
+  if constexpr (NC == 64) {
+    for (int r = 0; r < NC / 2; ++r) {
+      // two signed 16-bit fields, each within +-32767 (LAB_FLUSH_STEPS)
+      const int32_t w = lane < C ? (int32_t)L.hist[r * C + lane] : 0;
+      const int32_t lo = (int32_t)(int16_t)(uint16_t)(w & 0xFFFF), hi = (w - lo) >> 16;
+      const uint64_t slo = wave_sum64((uint64_t)(int64_t)lo), shi = wave_sum64((uint64_t)(int64_t)hi);
+      if (lane == 0) {
+        if (r > 0 && slo) atomicAdd(&acc[2 * r], (unsigned long long)slo);
+        if (shi) atomicAdd(&acc[2 * r + 1], (unsigned long long)shi);
+      }
+    }
+  } else {
+    for (int c = 1; c < NC; ++c) {
+      const uint64_t x = lane < C ? (uint64_t)(int64_t)(int32_t)L.hist[c * C + lane] : 0u;
+      const uint64_t sum = wave_sum64(x);
+      if (lane == 0 && sum) atomicAdd(&acc[c], (unsigned long long)sum);
+    }
   }
-  for (int c = 0; c < NC; ++c)
+  for (int c = 0; c < WaveLds<W, HH, NC>::ROWS; ++c)
     if (lane < C) L.hist[c * C + lane] = 0;
   wave_lds_sync();
 }
@@ -920,7 +952,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   WaveLds<W, HH, NC>& L = lds[threadIdx.x >> 6];
   const int64_t wave_id = (int64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
   if (g.wave_span && lane == 0) g.wave_span[2 * wave_id] = __builtin_amdgcn_s_memrealtime();
-  for (int c = 0; c < NC; ++c)
+  for (int c = 0; c < WaveLds<W, HH, NC>::ROWS; ++c)
     if (lane < C) L.hist[c * C + lane] = 0;
   wave_lds_sync();
   const uint32_t col = (uint32_t)(lane & (C - 1));
@@ -1035,11 +1067,15 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
         if (lane == 0 && cur.kind == 2) g.cycles[cur.tid] = (uint32_t)min(t_end - t_start, (uint64_t)0xFFFFFFFFu);
         t_start = t_end;
       }
-      if (steps > (1u << 30)) {
+      if (!LAB && steps > (1u << 30)) {
         pack_drain(L, pk, col);
         flush_wave(L, lane, BAT ? g.gout + 16 * (uint64_t)wg : g.acc);
         steps = 0;
       }
+    }
+    if (LAB && steps > LAB_FLUSH_STEPS) {
+      flush_wave(L, lane, g.acc);
+      steps = 0;
     }
     wave_lds_sync();
     if (!more) break;
@@ -1465,7 +1501,7 @@ static int group_grid() {
 // runs one launch shape: 448-entry windows, two wavefronts per workgroup.
 constexpr int LAB_WAVES = 2;
 static hipError_t launch_lab(const CensusArgs& a, int groups, hipStream_t s) {
-  k_census<LAB_WAVES, 448, true, 3, 3><<<groups, LAB_WAVES * 64, 0, s>>>(a);
+  k_census<LAB_WAVES, 448, true, 3, 5><<<groups, LAB_WAVES * 64, 0, s>>>(a);
   return hipGetLastError();
 }
 static int lab_groups(int requested) {
@@ -1473,7 +1509,7 @@ static int lab_groups(int requested) {
   DeviceInfo di;
   if (device_info(&di) != TRIAD_OK) return 1024;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<LAB_WAVES, 448, true, 3, 3>, LAB_WAVES * 64, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census<LAB_WAVES, 448, true, 3, 5>, LAB_WAVES * 64, 0) !=
           hipSuccess || per_cu < 1)
     per_cu = 1;
   return di.cus * per_cu;
