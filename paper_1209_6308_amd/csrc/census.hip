@@ -1497,8 +1497,9 @@ static int group_grid() {
   return di.cus * per_cu;
 }
 
-// The labelled census (64 counters per column: 8 KB of LDS per wavefront)
-// runs one launch shape: 448-entry windows, two wavefronts per workgroup.
+// The labelled census (64 state counters per column, two 16-bit counters per
+// LDS word: 4 KB per wavefront) runs one launch shape: 448-entry windows, two
+// wavefronts per workgroup, up to 5 per SIMD.
 constexpr int LAB_WAVES = 2;
 static hipError_t launch_lab(const CensusArgs& a, int groups, hipStream_t s) {
   k_census<LAB_WAVES, 448, true, 3, 5><<<groups, LAB_WAVES * 64, 0, s>>>(a);
