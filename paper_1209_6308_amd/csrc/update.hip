@@ -164,9 +164,34 @@ __device__ __forceinline__ int64_t find_change(const DeltaArgs& g, int64_t b, in
   return (p < e && (g.E[p] >> 4) == (k >> 4)) ? p : -1;
 }
 
+// Positions of the merged walk of N(a) and N(b) each lane takes per round.
+constexpr int UPD_S = 16;
+
+// Class change of the triad {a, b, w} for the third vertex w with old flags
+// g0a (a-w), g0b (b-w) and new ones g1a, g1b (cha, chb: that pair changes),
+// counted by the triad's smallest changed pair only.
+__device__ __forceinline__ void triad_move(const DeltaArgs& g, int32_t* h, int lane, uint64_t pk, int64_t a, int32_t b,
+                                           int32_t w, uint32_t f0, uint32_t f1, uint32_t g0a, uint32_t g1a, bool cha,
+                                           uint32_t g0b, uint32_t g1b, bool chb) {
+  bool own = true;
+  if (cha) own = own && pk < ((((uint64_t)min((int64_t)w, a)) << g.rb) | (uint64_t)max((int64_t)w, a));
+  if (chb) own = own && pk < ((((uint64_t)min(w, b)) << g.rb) | (uint64_t)max(w, b));
+  if (!own) return;
+  const uint32_t oc = class_of(g, f0 | g0a << 2 | g0b << 4), nc = class_of(g, f1 | g1a << 2 | g1b << 4);
+  if (oc != nc) {
+    h[oc * 64 + lane] -= 1;
+    h[nc * 64 + lane] += 1;
+  }
+}
+
 // One wavefront per changed pair {a, b} (the entries of row a in E). The third
-// vertices are taken from four sorted lists: N(a), the changes of a, N(b), the
-// changes of b; a vertex seen in an earlier list is skipped in a later one.
+// vertices are the union of four sorted lists: N(a), the changes of a, N(b),
+// the changes of b. N(a) and N(b) are walked together, merged in id order (a
+// merge path cut into 16 positions per lane and round, a common id consumed
+// once), so each vertex of either row comes with both old flags; a vertex
+// adjacent to b only whose pair with a changes is left to the pass over the
+// changes of a. The changes of a, then of b, follow, each vertex seen in an
+// earlier list skipped.
 __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
   __shared__ int32_t hist[UT / 64][16][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -188,41 +213,55 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
     const int64_t db0 = lower_key(g.E, 0, g.nE, (uint64_t)b << (g.rb + 4));
     const int64_t db1 = lower_key(g.E, db0, g.nE, (uint64_t)(b + 1) << (g.rb + 4));
     uint32_t ucount = 0;
-    for (int phase = 0; phase < 4; ++phase) {
-      const int64_t L0 = phase == 0 ? oa : phase == 1 ? da0 : phase == 2 ? ob : db0;
-      const int64_t L1 = phase == 0 ? ea : phase == 1 ? da1 : phase == 2 ? eb : db1;
+    // N(a) and N(b) merged
+    const int32_t* const A = g.nbr + oa;
+    const int32_t* const B = g.nbr + ob;
+    const int64_t la = ea - oa, lb = eb - ob, D = la + lb;
+    for (int64_t r0 = 0; r0 < D; r0 += 64 * UPD_S) {
+      const int64_t d0 = min(D, r0 + (int64_t)lane * UPD_S), d1 = min(D, d0 + UPD_S);
+      // merge-path split of diagonal d0: A elements among the first d0 merged
+      int64_t lo = d0 > lb ? d0 - lb : 0, hi = min(d0, la);
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (A[mid] <= B[d0 - mid - 1]) lo = mid + 1; else hi = mid;
+      }
+      int64_t i = lo, k = d0 - lo;
+      // an id shared by A[i-1] and B[k] was taken with A[i-1] by a lane before
+      if (i > 0 && k < lb && A[i - 1] == B[k]) ++k;
+      while (i + k < d1) {
+        const int32_t x = i < la ? A[i] : INT32_MAX, y = k < lb ? B[k] : INT32_MAX;
+        const bool inA = x <= y, inB = y <= x;
+        const int32_t w = inA ? x : y;
+        const uint32_t fa = inA ? entry_flag(g.flg, oa + i) : 0u, fb = inB ? entry_flag(g.flg, ob + k) : 0u;
+        i += inA;
+        k += inB;
+        if (w == a || w == b) continue;
+        uint32_t g1a = fa;
+        bool cha = false;
+        const int64_t pa = find_change(g, da0, da1, a, w);
+        if (pa >= 0) {
+          if (!inA) continue;  // a pair with a that changes: the pass over the changes of a takes w
+          cha = true;
+          g1a = (uint32_t)(g.E[pa] & 3u);
+        }
+        const int64_t pb = find_change(g, db0, db1, b, w);
+        const bool chb = pb >= 0;
+        const uint32_t g1b = chb ? (uint32_t)(g.E[pb] & 3u) : fb;
+        ++ucount;
+        triad_move(g, h, lane, pk, a, b, w, f0, f1, fa, g1a, cha, fb, g1b, chb);
+      }
+    }
+    // the changes of a (vertices not in N(a)), then of b (not in N(b), not seen before)
+    for (int phase = 1; phase < 4; phase += 2) {
+      const int64_t L0 = phase == 1 ? da0 : db0;
+      const int64_t L1 = phase == 1 ? da1 : db1;
       for (int64_t j0 = L0; j0 < L1; j0 += 64) {
         const int64_t j = j0 + lane;
         if (j >= L1) continue;
         int32_t w;
         uint32_t g0a = 0, g1a = 0, g0b = 0, g1b = 0;
         bool cha = false, chb = false, keep = true;
-        if (phase == 0 || phase == 2) {
-          w = g.nbr[j];
-          if (w == a || w == b) continue;
-          const uint32_t f = entry_flag(g.flg, j);
-          if (phase == 0) {
-            g0a = f;
-            const int64_t p = find_change(g, da0, da1, a, w);
-            cha = p >= 0;
-            g1a = cha ? (uint32_t)(g.E[p] & 3u) : g0a;
-          } else {
-            g0b = f;
-            // seen in N(a) or in the changes of a already?
-            const int64_t ja = lower_id(g.nbr, oa, ea, w);
-            keep = !(ja < ea && g.nbr[ja] == w) && find_change(g, da0, da1, a, w) < 0;
-            g0a = g1a = 0;
-          }
-          if (keep) {
-            if (phase == 0) {
-              const int64_t jb = lower_id(g.nbr, ob, eb, w);
-              g0b = (jb < eb && g.nbr[jb] == w) ? entry_flag(g.flg, jb) : 0u;
-            }
-            const int64_t p = find_change(g, db0, db1, b, w);
-            chb = p >= 0;
-            g1b = chb ? (uint32_t)(g.E[p] & 3u) : g0b;
-          }
-        } else {
+        {
           const uint64_t e = g.E[j];
           w = (int32_t)((e >> 4) & cmask);
           if (w == a || w == b) continue;
@@ -230,7 +269,7 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
             g0a = (e >> 2) & 3u;
             g1a = e & 3u;
             cha = true;
-            keep = g0a == 0;  // otherwise w is in N(a), seen in phase 0
+            keep = g0a == 0;  // otherwise w is in N(a), seen in the merged walk
             if (keep) {
               const int64_t jb = lower_id(g.nbr, ob, eb, w);
               g0b = (jb < eb && g.nbr[jb] == w) ? entry_flag(g.flg, jb) : 0u;
@@ -243,7 +282,7 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
             g1b = e & 3u;
             chb = true;
             if (g0b != 0) {
-              keep = false;  // in N(b), seen in phase 2
+              keep = false;  // in N(b), seen in the merged walk
             } else {
               const int64_t ja = lower_id(g.nbr, oa, ea, w);
               keep = !(ja < ea && g.nbr[ja] == w) && find_change(g, da0, da1, a, w) < 0;
@@ -252,16 +291,7 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
         }
         if (!keep) continue;
         ++ucount;
-        // the triad is counted by the smallest of its changed pairs
-        bool own = true;
-        if (cha) own = own && pk < ((((uint64_t)min((int64_t)w, a)) << g.rb) | (uint64_t)max((int64_t)w, a));
-        if (chb) own = own && pk < ((((uint64_t)min(w, b)) << g.rb) | (uint64_t)max(w, b));
-        if (!own) continue;
-        const uint32_t oc = class_of(g, f0 | g0a << 2 | g0b << 4), nc = class_of(g, f1 | g1a << 2 | g1b << 4);
-        if (oc != nc) {
-          h[oc * 64 + lane] -= 1;
-          h[nc * 64 + lane] += 1;
-        }
+        triad_move(g, h, lane, pk, a, b, w, f0, f1, g0a, g1a, cha, g0b, g1b, chb);
       }
     }
     // every other third vertex: only the pair {a, b} has arcs
