@@ -29,6 +29,7 @@
 #include <string>
 #include <vector>
 
+#include "tile_rows.h"
 #include "triad_internal.h"
 
 namespace triad {
@@ -296,28 +297,6 @@ __global__ void __launch_bounds__(256) k_hub_list(const uint64_t* __restrict__ t
     }
     __syncthreads();
   }
-}
-
-// Row of entry j: the last x in [lo, hi) with off[x] <= j, given off[lo] <= j
-// < off[hi] (an empty row is never the answer, since the row after it starts
-// at the same offset).
-__device__ __forceinline__ int64_t row_search(const int64_t* __restrict__ off, int64_t lo, int64_t hi, int64_t j) {
-  while (hi - lo > 1) {
-    const int64_t m = (lo + hi) >> 1;
-    if (off[m] <= j) lo = m; else hi = m;
-  }
-  return lo;
-}
-
-// Entry kernels take tiles of ETILE entries: two threads find the rows of the
-// tile's first and last entry over all offsets, and every entry then searches
-// only between those two rows.
-constexpr int ETILE = 4096;
-__device__ __forceinline__ void tile_rows(const int64_t* __restrict__ off, int64_t n, int64_t t0, int64_t t1,
-                                          int64_t* rr) {
-  __syncthreads();
-  if (threadIdx.x < 2) rr[threadIdx.x] = row_search(off, 0, n, threadIdx.x == 0 ? t0 : t1 - 1);
-  __syncthreads();
 }
 
 // Task list from the CSR entries, one thread per entry: entry j of row u with

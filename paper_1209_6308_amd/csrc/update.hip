@@ -36,6 +36,7 @@
 #include <string>
 
 #include "device_sort.h"
+#include "tile_rows.h"
 #include "triad_internal.h"
 
 namespace triad {
@@ -356,8 +357,6 @@ __global__ void k_new_offsets(int64_t n, int rb, const int64_t* __restrict__ off
   }
 }
 
-constexpr int COPY_TILE = 4096;
-
 // Old entries to their new places: rows without changes shift as a whole;
 // in a changed row an entry moves by the insertions and deletions before it,
 // takes its new flag, or is dropped.
@@ -367,29 +366,12 @@ __global__ void __launch_bounds__(UT) k_copy_old(int64_t n, int64_t nnz, int rb,
                                                  const uint32_t* __restrict__ I, const uint32_t* __restrict__ D,
                                                  const uint32_t* __restrict__ mark, const int64_t* __restrict__ noff,
                                                  int64_t nn, int32_t* __restrict__ nnbr, uint8_t* __restrict__ nfl) {
-  __shared__ int64_t rr[2];
-  for (int64_t t0 = (int64_t)blockIdx.x * COPY_TILE; t0 < nnz; t0 += (int64_t)gridDim.x * COPY_TILE) {
-    const int64_t t1 = min(t0 + COPY_TILE, nnz);
-    __syncthreads();
-    if (threadIdx.x < 2) {
-      // row of entry t0 / t1 - 1: last x with off[x] <= j
-      const int64_t j = threadIdx.x == 0 ? t0 : t1 - 1;
-      int64_t lo = 0, hi = n;
-      while (hi - lo > 1) {
-        const int64_t m = (lo + hi) >> 1;
-        if (off[m] <= j) lo = m; else hi = m;
-      }
-      rr[threadIdx.x] = lo;
-    }
-    __syncthreads();
-    const int64_t r0 = rr[0], r1 = rr[1];
+  __shared__ TileRows T;
+  for (int64_t t0 = (int64_t)blockIdx.x * ETILE; t0 < nnz; t0 += (int64_t)gridDim.x * ETILE) {
+    const int64_t t1 = min(t0 + (int64_t)ETILE, nnz);
+    tile_stage(off, n, t0, t1, T);
     for (int64_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
-      int64_t lo = r0, hi = r1 + 1;
-      while (hi - lo > 1) {
-        const int64_t m = (lo + hi) >> 1;
-        if (off[m] <= j) lo = m; else hi = m;
-      }
-      const int64_t x = lo;
+      const int64_t x = tile_row(off, T, t0, j);
       const int32_t y = nbr[j];
       uint32_t f = entry_flag(flg, j);
       int64_t pos = noff[x] + (j - off[x]);
@@ -583,7 +565,7 @@ int census_update(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
       k_row_marks<<<grid_of(nE, 256, 65536), 256, 0, s>>>(E, nE, rb, mark);
       k_new_offsets<<<grid_of(n + 1, 256, 65536), 256, 0, s>>>(n, rb, off, E, nE, I, D, noff);
       if (nnz > 0)
-        k_copy_old<<<grid_of(nnz, COPY_TILE, 65536), UT, 0, s>>>(n, nnz, rb, off, nbr, flg, E, nE, I, D, mark, noff,
+        k_copy_old<<<grid_of(nnz, ETILE, 65536), UT, 0, s>>>(n, nnz, rb, off, nbr, flg, E, nE, I, D, mark, noff,
                                                                  nn, nnbr, nf8);
       k_insert_new<<<grid_of(nE, 256, 65536), 256, 0, s>>>(rb, off, nbr, E, nE, I, D, noff, nn, nnbr, nf8);
       k_pack_bytes<<<grid_of((nn + 3) / 4, 256, 65536), 256, 0, s>>>(nf8, nn, nflg);
