@@ -15,7 +15,8 @@
 //   radix sort      least-significant-digit first, 8-bit digits, stable:
 //                   k_rs_hist (per-tile digit counts), an exclusive scan of
 //                   the digit-major counts, k_rs_scatter (per-wave ranks by
-//                   ballot matching, per-wave running counts in LDS)
+//                   ballot matching, per-wave running counts in LDS, the tile
+//                   laid out in digit order in LDS and written in runs)
 //   k_head_count    per tile, the first keys of (row, col) runs
 //   k_emit_csr      ids, run-first and run-last bits, row offsets
 //   k_pack_flags    2-bit flags, four per byte
@@ -35,6 +36,7 @@ constexpr int RS_ITEMS = 16;                         // keys per thread and tile
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;       // 4,096 keys
 constexpr int RS_WAVE_KEYS = RS_TILE / RS_WAVES;     // 1,024 consecutive keys per wavefront
 constexpr int RS_ROUNDS = RS_WAVE_KEYS / 64;         // 16 rounds of 64
+static_assert(RS_THREADS == RS_BUCKETS, "the scatter gives each digit one thread");
 
 __device__ __forceinline__ int bit_width_u(uint64_t x) { return x ? 64 - __clzll((long long)x) : 0; }
 
@@ -89,17 +91,22 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t* __restri
 // Stable scatter of one tile. Wavefront w owns keys [w * 1024, (w+1) * 1024)
 // of the tile, 64 per round in order; a key's rank among the equal digits
 // before it in its wavefront comes from ballots that match the digit bit by
-// bit, and per-wavefront running counts in LDS carry it across rounds; the
-// wavefronts' counts are then prefixed per digit, so the tile keeps input
-// order within each digit.
+// bit, and per-wavefront running counts in LDS carry it across rounds. The
+// tile is then laid out in LDS in digit order (digit starts from a scan of the
+// tile's counts, the wavefronts of one digit in order), and written out from
+// there: consecutive threads write consecutive keys, so each digit's keys of
+// the tile leave as one contiguous run. Input order within a digit is kept.
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
                                                            int64_t N, int shift, const uint32_t* __restrict__ offs,
                                                            int64_t ntiles) {
   __shared__ uint32_t cnt[RS_WAVES][RS_BUCKETS];
+  __shared__ uint32_t lstart[RS_BUCKETS], gstart[RS_BUCKETS], wsum[RS_WAVES + 1];
+  __shared__ uint64_t buf[RS_TILE];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int k = threadIdx.x; k < RS_WAVES * RS_BUCKETS; k += RS_THREADS) (&cnt[0][0])[k] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * RS_WAVE_KEYS;
+  const int64_t tbase = (int64_t)blockIdx.x * RS_TILE;
+  const int64_t base = tbase + (int64_t)w * RS_WAVE_KEYS;
   const uint64_t below = (1ull << lane) - 1;
   uint64_t key[RS_ROUNDS];
   uint32_t pos[RS_ROUNDS];
@@ -127,25 +134,53 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t* __res
     pos[r] = c + (uint32_t)__popcll(m & below);
   }
   __syncthreads();
-  // per digit: the counts of the wavefronts before, plus the tile's offset
-  {
-    const int d = threadIdx.x;
-    uint32_t s = offs[(int64_t)d * ntiles + blockIdx.x];
+  // per digit (one thread each): the tile's count, its global start, and the
+  // wavefronts' starts within the digit
+  const int d = threadIdx.x;
+  uint32_t tot = 0;
 #pragma unroll
+  for (int q = 0; q < RS_WAVES; ++q) {
+    const uint32_t c = cnt[q][d];
+    cnt[q][d] = tot;
+    tot += c;
+  }
+  gstart[d] = offs[(int64_t)d * ntiles + blockIdx.x];
+  // exclusive scan of the tile's digit counts across the block
+  uint32_t x = tot;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
     for (int q = 0; q < RS_WAVES; ++q) {
-      const uint32_t c = cnt[q][d];
-      cnt[q][d] = s;
-      s += c;
+      const uint32_t t = wsum[q];
+      wsum[q] = run;
+      run += t;
     }
   }
   __syncthreads();
+  lstart[d] = x - tot + wsum[w];
+  __syncthreads();
+  // the tile in digit order in LDS
 #pragma unroll
   for (int r = 0; r < RS_ROUNDS; ++r) {
     const int64_t i = base + (int64_t)r * 64 + lane;
     if (i < N) {
-      const uint32_t at = cnt[w][(uint32_t)(key[r] >> shift) & (RS_BUCKETS - 1)] + pos[r];
-      if (at < (uint64_t)N) out[at] = key[r];  // always true; keeps a faulty rank in bounds
+      const uint32_t dk = (uint32_t)(key[r] >> shift) & (RS_BUCKETS - 1);
+      const uint32_t at = lstart[dk] + cnt[w][dk] + pos[r];
+      if (at < (uint32_t)RS_TILE) buf[at] = key[r];  // always true; keeps a faulty rank in bounds
     }
+  }
+  __syncthreads();
+  const int64_t nt = min((int64_t)RS_TILE, N - tbase);
+  for (int i = threadIdx.x; i < nt; i += RS_THREADS) {
+    const uint64_t k = buf[i];
+    const uint32_t dk = (uint32_t)(k >> shift) & (RS_BUCKETS - 1);
+    const uint64_t at = (uint64_t)gstart[dk] + (uint32_t)(i - lstart[dk]);
+    if (at < (uint64_t)N) out[at] = k;  // always true; keeps a faulty rank in bounds
   }
 }
 
