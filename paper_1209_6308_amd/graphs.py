@@ -319,3 +319,32 @@ def randomised_ensemble(g: CSR, K: int, seed: int = 1, swap_factor: float = 10.0
     members = [build_csr(g.n, out_s[k * m:(k + 1) * m], out_d[k * m:(k + 1) * m]) for k in range(K)]
     return concat_csrs(members)
 
+
+
+def window_batches(n: int, src: np.ndarray, dst: np.ndarray, times: np.ndarray, width: float, step: float,
+                   t_end: float):
+    """Update batches that keep a census of a sliding time window over a stream
+    of timestamped arcs (the census at fixed intervals of Sec. 3): the window
+    [t, t + width) moves by `step` from t = 0 while t + width <= t_end. An arc
+    is present while any of its occurrences lies in the window, so each step's
+    batch is the difference of the two windows' arc sets: deletions of the arcs
+    that left it, insertions of those that entered (self-loops never count).
+    Yields (start time, src, dst, insert) per step, the first step the whole
+    first window as insertions."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    times = np.asarray(times, dtype=np.float64)
+    keep = src != dst
+    src, dst, times = src[keep], dst[keep], times[keep]
+    key = src * n + dst
+    prev = np.zeros(0, dtype=np.int64)
+    t = 0.0
+    while t + width <= t_end:
+        cur = np.unique(key[(times >= t) & (times < t + width)])
+        gone = np.setdiff1d(prev, cur, assume_unique=True)
+        came = np.setdiff1d(cur, prev, assume_unique=True)
+        k = np.concatenate([gone, came])
+        ins = np.concatenate([np.zeros(gone.size, np.uint8), np.ones(came.size, np.uint8)])
+        yield t, (k // n).astype(np.int32), (k % n).astype(np.int32), ins
+        prev = cur
+        t += step

@@ -179,3 +179,27 @@ def test_rmat24_batch_and_its_inverse(torch):
     c2, csr2, _ = triad.census_update(n, nnz1, *csr1, c1, us, ud, (1 - ins).contiguous())
     assert c2 == want
     assert torch.equal(csr2[0], off) and torch.equal(csr2[1], nbr) and torch.equal(csr2[2], flg)
+
+
+def test_sliding_window_series(torch):
+    """Windowed census: a stream of timestamped arcs (R-MAT endpoints, uniform
+    times), a window of 20 time units moved by 5; each step's batch (arcs that
+    left the window deleted, arcs that entered inserted) brings the census of
+    the previous window to the oracle's census of the new window's arc set."""
+    n = 1 << 9
+    src, dst = graphs.rmat_arcs(9, 40000, seed=4)
+    times = np.random.default_rng(6).uniform(0.0, 100.0, src.size)
+    g = graphs.build_csr(n, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    dev, nnz = triad.to_device(g), 0
+    census = oracle.census(g)
+    steps = 0
+    for t, us, ud, ui in graphs.window_batches(n, src, dst, times, 20.0, 5.0, 100.0):
+        args = [torch.from_numpy(a).cuda() for a in (us, ud, ui)]
+        census, dev, _ = triad.census_update(n, nnz, *dev, census, *args)
+        nnz = int(dev[1].numel())
+        sel = (times >= t) & (times < t + 20.0)
+        want = graphs.build_csr(n, src[sel], dst[sel])
+        assert census == oracle.census(want), t
+        assert np.array_equal(dev[0].cpu().numpy(), want.offsets)
+        steps += 1
+    assert steps == 17

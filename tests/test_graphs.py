@@ -148,3 +148,25 @@ def test_randomised_ensemble_keeps_degrees():
     assert changed == B.G  # every copy was rewired
     again = graphs.randomised_ensemble(g, 6, seed=2)
     assert again.content_hash() == B.content_hash()
+
+
+def test_window_batches_follow_the_window():
+    """Applying each step's batch to a set of arcs (delete, then insert) gives
+    exactly the arc set of the new window; no batch touches an arc twice."""
+    n = 1 << 9
+    src, dst = graphs.rmat_arcs(9, 20000, seed=4)
+    times = np.random.default_rng(6).uniform(0.0, 100.0, src.size)
+    cur, steps = set(), 0
+    for t, us, ud, ui in graphs.window_batches(n, src, dst, times, 20.0, 5.0, 100.0):
+        pairs = list(zip(us.tolist(), ud.tolist()))
+        assert len(set(pairs)) == len(pairs)
+        for (a, b), i in zip(pairs, ui.tolist()):
+            if i:
+                assert (a, b) not in cur
+                cur.add((a, b))
+            else:
+                cur.remove((a, b))
+        sel = (times >= t) & (times < t + 20.0) & (src != dst)
+        assert cur == set(zip(src[sel].tolist(), dst[sel].tolist()))
+        steps += 1
+    assert steps == 17
