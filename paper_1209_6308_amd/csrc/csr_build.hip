@@ -3,13 +3,15 @@
 //
 // Every arc (x, y), x != y, yields two entries: row x sees y with bit0 (x->y)
 // and row y sees x with bit1 (x->y seen from y). An entry is one 64-bit key
-//     row << (RB + 2) | col << 2 | bit,   RB = bit width of n,
-// so sorting the keys orders the entries by row, then column, then direction
-// bit. A self-loop yields two keys of the row n, which sort after every real
-// entry and are dropped. After the sort, a run of equal (row, col) keys is one
-// neighbour; its flag is the OR of its bits, which (the bits being sorted
-// within the run) is the first key's bit OR the last key's bit. Duplicate arcs
-// are thereby merged, and each pair's two rows get mirrored flags.
+//     row << (RB + 2) | col << 2 | bit,   RB = bit width of n - 1,
+// and the keys are sorted on their (row, col) bits only, so the entries come
+// in order of row, then column. A self-loop yields two keys whose (row, col)
+// bits are all ones, which sort after every real entry (a real pair never has
+// row = col) and are dropped. After the sort, a run of equal (row, col) keys
+// is one neighbour; its flag is the OR of its keys' bits, recorded by every
+// key of the run (one byte per direction and entry, written with the same
+// value by each key that has that bit). Duplicate arcs are thereby merged,
+// and each pair's two rows get mirrored flags.
 //
 //   k_arc_keys      two keys per arc, range check, self-loop count
 //   radix sort      least-significant-digit first, 8-bit digits, stable:
@@ -18,7 +20,7 @@
 //                   ballot matching, per-wave running counts in LDS, the tile
 //                   laid out in digit order in LDS and written in runs)
 //   k_head_count    per tile, the first keys of (row, col) runs
-//   k_emit_csr      ids, run-first and run-last bits, row offsets
+//   k_emit_csr      ids, the runs' direction bits, row offsets
 //   k_pack_flags    2-bit flags, four per byte
 #include <hip/hip_runtime.h>
 
@@ -44,7 +46,7 @@ __global__ void k_arc_keys(int64_t n, int64_t narcs, int rb, const int32_t* __re
                            const int32_t* __restrict__ dst, uint64_t* __restrict__ keys,
                            unsigned long long* __restrict__ loops, uint32_t* __restrict__ err) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const uint64_t drop = (uint64_t)n << (rb + 2);
+  const uint64_t drop = ((1ull << (2 * rb)) - 1) << 2;  // (row, col) all ones: sorts last
   uint32_t bad = 0;
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < narcs; i0 += stride) {
     const int64_t i = i0 + threadIdx.x;
@@ -327,10 +329,11 @@ __global__ void __launch_bounds__(RS_THREADS) k_head_count(const uint64_t* __res
   }
 }
 
-// Entry e of the CSR is the e-th run. Its head writes the column and the run's
-// first direction bit, its last key the last bit; the head of a row's first
-// run writes the offsets of that row and of the empty rows before it, the
-// last valid key those of the rows after its own.
+// Entry e of the CSR is the e-th run. Its head writes the column; every key of
+// the run marks its direction bit (fh[e] = 1 for bit0, ft[e] = 2 for bit1, both
+// zeroed before); the head of a row's first run writes the offsets of that row
+// and of the empty rows before it, the last valid key those of the rows after
+// its own.
 __global__ void __launch_bounds__(RS_THREADS) k_emit_csr(const uint64_t* __restrict__ key, int64_t nvalid, int64_t n,
                                                          int rb, const uint32_t* __restrict__ tileoff, uint32_t nnz,
                                                          int64_t* __restrict__ off, int32_t* __restrict__ nbr,
@@ -363,12 +366,12 @@ __global__ void __launch_bounds__(RS_THREADS) k_emit_csr(const uint64_t* __restr
       const uint8_t bitv = (uint8_t)(k & 3u);
       if (head) {
         nbr[e] = (int32_t)((k >> 2) & colmask);
-        fh[e] = bitv;
         const int64_t prev = i == 0 ? -1 : (int64_t)(key[i - 1] >> (rb + 2));
         for (int64_t x = prev + 1; x <= row; ++x) off[x] = e;
       }
+      if (bitv & 1u) fh[e] = 1;
+      if (bitv & 2u) ft[e] = 2;
       const bool last = i + 1 == nvalid;
-      if (last || run_head(key, i + 1)) ft[e] = bitv;
       if (last)
         for (int64_t x = row + 1; x <= n; ++x) off[x] = nnz;
     }
@@ -437,7 +440,7 @@ int csr_from_arcs(int64_t n, int64_t narcs, const int32_t* src, const int32_t* d
     return done(0);
   }
   Scratch scratch(s);
-  const int rb = std::max(1, 64 - __builtin_clzll((unsigned long long)n));  // n < 2^rb
+  const int rb = n > 1 ? 64 - __builtin_clzll((unsigned long long)(n - 1)) : 1;  // ids below 2^rb
   const int64_t N = 2 * narcs;
   uint64_t *ka = nullptr, *kb = nullptr;
   uint32_t* err = nullptr;
@@ -456,8 +459,9 @@ int csr_from_arcs(int64_t n, int64_t narcs, const int32_t* src, const int32_t* d
   HIPCHK(hipMemcpyAsync(&nloops, loops, sizeof nloops, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (errh) return fail(TRIAD_ERANGE, "arc endpoint outside [0, n)");
-  // radix sort over bits [0, 2 + 2 rb): direction bit, column, row
-  if (int st = radix_sort_u64(&ka, &kb, N, 0, 2 + 2 * rb, scratch, s)) return st;
+  // radix sort over bits [2, 2 + 2 rb): column, row (the direction bits are
+  // merged per run, not sorted)
+  if (int st = radix_sort_u64(&ka, &kb, N, 2, 2 + 2 * rb, scratch, s)) return st;
   // runs of equal (row, col): one CSR entry each
   const int64_t nvalid = N - 2 * (int64_t)nloops;
   const int64_t vt = std::max<int64_t>(1, (nvalid + RS_TILE - 1) / RS_TILE);
@@ -480,8 +484,10 @@ int csr_from_arcs(int64_t n, int64_t narcs, const int32_t* src, const int32_t* d
     return done(0);
   }
   uint8_t *fh = nullptr, *ft = nullptr;
-  ALLOC(fh, nnz);
-  ALLOC(ft, nnz);
+  ALLOC(fh, (int64_t)nnz + 4);
+  ALLOC(ft, (int64_t)nnz + 4);
+  k_zero_words<<<grid_of(((int64_t)nnz + 4) / 4, 256, 65536), 256, 0, s>>>((uint32_t*)fh, ((int64_t)nnz + 4) / 4);
+  k_zero_words<<<grid_of(((int64_t)nnz + 4) / 4, 256, 65536), 256, 0, s>>>((uint32_t*)ft, ((int64_t)nnz + 4) / 4);
   k_emit_csr<<<(unsigned)vt, RS_THREADS, 0, s>>>(ka, nvalid, n, rb, tileoff, nnz, off, nbr, fh, ft);
   k_pack_flags<<<grid_of((nnz + 3) / 4, 256, 65536), 256, 0, s>>>(fh, ft, nnz, flg);
   HIPCHK(hipGetLastError());
