@@ -239,13 +239,14 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
         if (w == a || w == b) continue;
         uint32_t g1a = fa;
         bool cha = false;
-        const int64_t pa = find_change(g, da0, da1, a, w);
+        // (a change list holding only the pair {a, b} itself has no entry for w)
+        const int64_t pa = da1 - da0 > 1 ? find_change(g, da0, da1, a, w) : -1;
         if (pa >= 0) {
           if (!inA) continue;  // a pair with a that changes: the pass over the changes of a takes w
           cha = true;
           g1a = (uint32_t)(g.E[pa] & 3u);
         }
-        const int64_t pb = find_change(g, db0, db1, b, w);
+        const int64_t pb = db1 - db0 > 1 ? find_change(g, db0, db1, b, w) : -1;
         const bool chb = pb >= 0;
         const uint32_t g1b = chb ? (uint32_t)(g.E[pb] & 3u) : fb;
         ++ucount;
