@@ -741,6 +741,9 @@ struct FlagPack {
   uint32_t acc;     // per lane: byte f = ids of flag f counted since the drain
   uint32_t tbl;     // the class row those counts belong to (uniform)
   uint32_t rounds;  // rounds counted since the drain (uniform)
+  // labelled census: ids above v in acc, the rest in acc0 (byte 0 of both
+  // collects the uncounted ids); tbl and tbl0 are the state tables of the two
+  uint32_t acc0, tbl0;
 };
 template <int W>
 constexpr uint32_t pack_rounds() {
@@ -751,10 +754,20 @@ template <int W, bool HH, int NC>
 __device__ __forceinline__ void pack_drain(WaveLds<W, HH, NC>& L, FlagPack& p, uint32_t col) {
   static_assert(pack_rounds<W>() * (W / 64) < 256, "a byte counter would overflow");
   constexpr uint32_t C = WaveLds<W, HH, NC>::COLS;
-  if (NC == 64 || p.rounds == 0) return;  // (the labelled census never packs)
+  if (p.rounds == 0) return;
   uint32_t* const hcol = L.hist + col;
+  if constexpr (NC == 64) {
+    // state of flag f: 6-bit field f of the table (8-bit fields; field 0 unused)
 #pragma unroll
-  for (uint32_t f = 1; f < 4; ++f) atomicAdd(hcol + ((p.tbl >> (4 * f)) & 15u) * C, (p.acc >> (8 * f)) & 255u);
+    for (uint32_t f = 1; f < 4; ++f) {
+      hist_add<W, HH, NC>(hcol, (p.tbl >> (8 * f)) & 63u, (p.acc >> (8 * f)) & 255u);
+      hist_add<W, HH, NC>(hcol, (p.tbl0 >> (8 * f)) & 63u, (p.acc0 >> (8 * f)) & 255u);
+    }
+    p.acc0 = 0;
+  } else {
+#pragma unroll
+    for (uint32_t f = 1; f < 4; ++f) atomicAdd(hcol + ((p.tbl >> (4 * f)) & 15u) * C, (p.acc >> (8 * f)) & 255u);
+  }
   p.acc = 0;
   p.rounds = 0;
 }
@@ -835,6 +848,28 @@ __device__ __forceinline__ void lopsided_round(WaveLds<W, HH, NC>& L, uint32_t n
     // depending on the side of v; N(u) only counts above v. Tables hold the
     // state per flag in 8-bit fields (field 0 = uncounted).
     const uint32_t thi = sA ? lt.gb_hi[fuv] : lt.ga_hi[fuv], tlo = sA ? lt.gb_lo[fuv] : 0u;
+    if (ng == (uint32_t)W) {
+      // a full window: all reads first, then per-lane byte counts by flag and
+      // side of v (an uncounted id into byte 0), drained when the tables change
+      uint32_t y[W / 64];
+#pragma unroll
+      for (int j = 0; j < W / 64; ++j) y[j] = G[j * 64 + lane];
+      if (pk.tbl != thi || pk.tbl0 != tlo || pk.rounds >= pack_rounds<W>()) {
+        pack_drain(L, pk, col);
+        pk.tbl = thi;
+        pk.tbl0 = tlo;
+      }
+      uint32_t a1 = pk.acc, a0 = pk.acc0;
+#pragma unroll
+      for (int j = 0; j < W / 64; ++j) {
+        const uint32_t inc = 1u << (((y[j] > thrG ? y[j] : 0u) << 3) & 31u);
+        if (y[j] > vq) a1 += inc; else a0 += inc;
+      }
+      pk.acc = a1;
+      pk.acc0 = a0;
+      pk.rounds += 1;
+      return;
+    }
     for (uint32_t e = (uint32_t)lane; e - (uint32_t)lane < ng; e += 64) {
       const uint32_t y = G[e < ng ? e : 0];
       const uint32_t off = ((e < ng) & (y > thrG)) ? y << 3 : 0u;
@@ -960,7 +995,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
   uint64_t t_start = CYC ? __builtin_amdgcn_s_memtime() : 0;
   uint32_t ra[W / 64], rb[W / 64];
   uint32_t na_ld = 0, nb_ld = 0;
-  FlagPack pk{0u, 0u, 0u};
+  FlagPack pk{0u, 0u, 0u, 0u, 0u};
 
   for (;;) {
     // ---- stage the loaded round in LDS (slots past the window get zeros or
@@ -1053,6 +1088,7 @@ __global__ void __launch_bounds__(WAVES * 64, MINW) k_census(CensusArgs g) {
       }
     }
     if (LAB && steps > LAB_FLUSH_STEPS) {
+      pack_drain(L, pk, col);  // counts still packed belong to the rounds steps covers
       flush_wave(L, lane, g.acc);
       steps = 0;
     }
