@@ -472,8 +472,7 @@ def batched_bench(torch, reps=3):
     m_sym = B.nnz // 2
     log(f"generated the ensemble in {time.time() - t0:.1f}s: {B.G} graphs, {nv} vertices, {m_sym} edges")
     d = triad.batch_to_device(B)
-    cache = os.path.join(ROOT, "gpurun_out", "batch_tune.jsonl") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) \
-        else None
+    cache = os.environ.get("TRIAD_TUNE_CACHE") or None  # a JSON-lines file of tuned launch shapes, if given
     t0 = time.time()
     best = triad.batch_autotune(B.G, nv, B.nnz, *d, cache_path=cache)
     tune_s = time.time() - t0
