@@ -29,6 +29,7 @@
 #include <string>
 #include <vector>
 
+#include "device_sort.h"
 #include "tile_rows.h"
 #include "triad_internal.h"
 
@@ -222,11 +223,16 @@ struct EmitArgs {
   int32_t count_below;    // 0: write 0 to tskip (the merge then takes all of N(v))
   int64_t hub_threshold;  // < 0: no hub tasks
   const uint32_t* err;
+  // optional: every entry below its row's own id, as (id << 32 | index in the
+  // row), at lpre[row] + index (lpre: exclusive prefix of those counts)
+  uint64_t* lower;
+  const int64_t* lpre;
 };
 
 // One task per active lane: row u (entries from b, degree du), k = index of v
 // in the row, t = task index. Also records how many ids of N(v) lie below u
-// (binary search in N(v)): a whole task's merge starts N(v) at u.
+// (binary search in N(v)): a whole task's merge starts N(v) at u. With the
+// lower entries listed (e.lower), those counts come from their sort instead.
 __device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int64_t u, int64_t b, int64_t du, uint32_t k,
                                           int64_t t) {
   if (!act) return;
@@ -248,7 +254,7 @@ __device__ __forceinline__ void emit_task(const EmitArgs& e, bool act, int64_t u
       len = half;
     }
   }
-  e.tskip[t] = lo;
+  if (!e.lower) e.tskip[t] = lo;
 }
 
 // Hub list: the flagged tasks, compacted with one atomic per tile of HUB_TILE
@@ -289,7 +295,8 @@ __global__ void __launch_bounds__(256) k_hub_list(const uint64_t* __restrict__ t
         const int64_t au = off[u], du = off[u + 1] - au;
         const uint32_t v = packed[au + k] >> 2;
         // the merged length: N(u) above u and N(v) from u on
-        const int64_t len = (du - ustart[u]) + (off[v + 1] - off[v]) - tskip[t];
+        const int64_t dv = off[v + 1] - off[v];
+        const int64_t len = (du - ustart[u]) + dv - min((int64_t)tskip[t], dv);
         hub_task[h] = (uint64_t)t;
         hub_nch[h] = (len + chunk - 1) / chunk;
       }
@@ -314,9 +321,24 @@ __global__ void __launch_bounds__(256) k_emit_entries(EmitArgs e, int64_t nnz) {
       const int64_t u = row_search(e.off, r0, r1 + 1, j);
       const int64_t b = e.off[u];
       const uint32_t k = (uint32_t)(j - b), su = e.ustart[u];
-      if (k >= su) emit_task(e, true, u, b, e.off[u + 1] - b, k, e.tpre[u] + (k - su));
+      if (k >= su)
+        emit_task(e, true, u, b, e.off[u + 1] - b, k, e.tpre[u] + (k - su));
+      else if (e.lower)
+        e.lower[e.lpre[u] + k] = ((uint64_t)(e.packed[j] >> 2) << 32) | k;
     }
   }
+}
+
+// Per row: the number of its entries below its own id (as 64-bit counts for the scan).
+__global__ void k_lower_counts(int64_t n, const uint32_t* __restrict__ ustart, int64_t* __restrict__ cnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) cnt[x] = ustart[x];
+}
+
+// tskip[t] = the low word of the t-th sorted lower entry.
+__global__ void k_low_words(const uint64_t* __restrict__ items, int64_t m, uint32_t* __restrict__ tskip) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += stride) tskip[t] = (uint32_t)items[t];
 }
 
 static void launch_emit_entries(const EmitArgs& e, int64_t nnz, hipStream_t s) {
@@ -1695,8 +1717,29 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     ALLOC(hub_task, hub_cap);
     ALLOC(hub_nch, hub_cap);
     ALLOC(hub_pre, hub_cap + 1);
-    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, 1, hub_thr, err};
+    // Each task's count of N(v) ids below u. The entries of row v below v,
+    // listed in CSR order, are the tasks (w, v) with that count as their index
+    // in the row; sorted by w (stably, so v stays in order within each w) they
+    // come out in task order, and their indices are the counts. The
+    // no-allocation census, whose scratch is bounded, searches u in N(v) per
+    // task instead.
+    const bool by_sort = !arena && ntasks < ((int64_t)1 << 32);
+    uint64_t *items = nullptr, *itmp = nullptr;
+    int64_t* lpre = nullptr;
+    if (by_sort) {
+      ALLOC(items, ntasks);
+      ALLOC(itmp, ntasks);
+      ALLOC(lpre, n + 1);
+      k_lower_counts<<<grid_for(n, 256), 256, 0, s>>>(n, ustart, ntask);
+      if (int st = scan_excl(ntask, n, lpre, scratch, s)) return st;
+    }
+    const EmitArgs e{n, off, packed, ustart, tpre, tasks, tskip, by_sort ? 0 : 1, hub_thr, err, items, lpre};
     launch_emit_entries(e, nnz, s);
+    if (by_sort) {
+      const int rbu = n > 1 ? 64 - __builtin_clzll((unsigned long long)(n - 1)) : 1;  // ids below 2^rbu
+      if (int st = radix_sort_u64(&items, &itmp, ntasks, 32, 32 + rbu, scratch, s)) return st;
+      k_low_words<<<grid_for(ntasks, 256, 65536), 256, 0, s>>>(items, ntasks, tskip);
+    }
     // A schedule reorders the last batches of the queue: in place, or, with
     // per-task cycle recording, through a queue-position -> task index map
     // that keeps the tasks (and so the cycles) in CSR order.
@@ -2081,7 +2124,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
     if (ntasks > 0) {
       // the ids of N(v) below u are counted (the merge starts N(v) at u) when
       // the short tasks run grouped, where every merged entry weighs
-      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, grouped ? 1 : 0, -1, p->err};
+      const EmitArgs ea{nv, off, packed, ustart, tpre, tasks, tskip, grouped ? 1 : 0, -1, p->err, nullptr, nullptr};
       launch_emit_entries(ea, nnz, s);
       if (grouped) {
         GroupArgs ga{};

@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(256) k_batch_keys(int mode, const float* __res
         dp = du - ustart[u];
         const uint32_t v = packed[au + k] >> 2;
         dv = (uint32_t)(off[v + 1] - off[v]);
-        sv = tskip[t];
+        sv = min(tskip[t], dv);
         above = du - k - 1;
         live = true;
       }
