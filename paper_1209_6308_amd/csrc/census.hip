@@ -1874,21 +1874,32 @@ __global__ void k_rows_batch(int32_t G, int64_t nv, int64_t nnz, const int64_t* 
 
 // Per entry of a batch: graph-local id in range, flag not 0, rows strictly
 // increasing, and the packed word with the id moved to the disjoint union
-// (graph base added).
-__global__ void __launch_bounds__(256) k_entries_batch(int64_t nv, int64_t nnz, const int64_t* __restrict__ vbase,
+// (graph base added). An entry's graph is the last one whose first entry
+// (off[vbase[g]]) is not after it; a tile of ETILE entries usually lies in one
+// graph (found once per tile), else its entries search the tile's few graphs.
+__device__ __forceinline__ int32_t graph_of_entry(const int64_t* __restrict__ off, const int64_t* __restrict__ vbase,
+                                                  int32_t lo, int32_t hi, int64_t j) {
+  // off[vbase[lo]] <= j; the answer lies in [lo, hi)
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (off[vbase[mid]] <= j) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+__global__ void __launch_bounds__(256) k_entries_batch(int32_t G, int64_t nnz, const int64_t* __restrict__ vbase,
                                                        const int64_t* __restrict__ off, const int32_t* __restrict__ nbr,
-                                                       const uint8_t* __restrict__ flg, const uint32_t* __restrict__ grow,
+                                                       const uint8_t* __restrict__ flg,
                                                        const uint32_t* __restrict__ rowmark,
                                                        uint32_t* __restrict__ packed, uint32_t* __restrict__ err) {
-  __shared__ int64_t rr[2];
+  __shared__ int32_t gr[2];
   uint32_t bits = 0;
   for (int64_t t0 = (int64_t)blockIdx.x * ETILE; t0 < nnz; t0 += (int64_t)gridDim.x * ETILE) {
     const int64_t t1 = min(t0 + (int64_t)ETILE, nnz);
-    tile_rows(off, nv, t0, t1, rr);
-    const int64_t r0 = rr[0], r1 = rr[1];
+    if (threadIdx.x < 2) gr[threadIdx.x] = graph_of_entry(off, vbase, 0, G, threadIdx.x ? t1 - 1 : t0);
+    __syncthreads();
+    const int32_t ga = gr[0], gb = gr[1];
     for (int64_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
-      const int64_t x = row_search(off, r0, r1 + 1, j);
-      const uint32_t gx = grow[x];
+      const int32_t gx = ga == gb ? ga : graph_of_entry(off, vbase, ga, gb + 1, j);
       const int64_t g0 = vbase[gx], ng = vbase[gx + 1] - g0;
       const int32_t y = nbr[j];
       const uint32_t f = (flg[j >> 2] >> (2 * (j & 3))) & 3u;
@@ -1899,6 +1910,7 @@ __global__ void __launch_bounds__(256) k_entries_batch(int64_t nv, int64_t nnz, 
       }
       packed[j] = ((uint32_t)(y + g0) << 2) | f;
     }
+    __syncthreads();
   }
   if (bits) atomicOr(err, bits);
 }
@@ -2117,7 +2129,7 @@ static int plan_build(int32_t G, int64_t nv, int64_t nnz, const int64_t* vbase, 
     k_rows_batch<<<grid_for(nv, 256, 65535), 256, 0, s>>>(G, nv, nnz, vbase, off, nbr, grow, ustart, ntask, rowmark,
                                                           p->err);
     if (nnz > 0)
-      k_entries_batch<<<grid_for(nnz, ETILE, 65536), 256, 0, s>>>(nv, nnz, vbase, off, nbr, flg, grow, rowmark, packed,
+      k_entries_batch<<<grid_for(nnz, ETILE, 65536), 256, 0, s>>>(G, nnz, vbase, off, nbr, flg, rowmark, packed,
                                                                  p->err);
     scan_excl_pre(ntask, nv, tpre, bsum, s);
     k_check_tasks<<<1, 64, 0, s>>>(tpre, nv, nnz, p->err);
