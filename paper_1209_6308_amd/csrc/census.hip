@@ -27,6 +27,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device_sort.h"
@@ -310,15 +311,26 @@ __global__ void __launch_bounds__(256) k_hub_list(const uint64_t* __restrict__ t
 // an id above u is task tpre[u] + (j - off[u] - ustart[u]) (CSR order), with
 // its count of N(v) ids below u and its hub flag (emit_task). Every task is
 // as cheap as the next, whatever the lengths of the rows.
+// STAGED: the tile's row starts come from LDS (the sort path, whose entries do
+// no global search of their own).
+template <bool STAGED>
 __global__ void __launch_bounds__(256) k_emit_entries(EmitArgs e, int64_t nnz) {
-  __shared__ int64_t rr[2];
+  __shared__ typename std::conditional<STAGED, TileRows, int64_t[2]>::type T;
   if (*e.err) return;
   for (int64_t t0 = (int64_t)blockIdx.x * ETILE; t0 < nnz; t0 += (int64_t)gridDim.x * ETILE) {
     const int64_t t1 = min(t0 + (int64_t)ETILE, nnz);
-    tile_rows(e.off, e.n, t0, t1, rr);
-    const int64_t r0 = rr[0], r1 = rr[1];
+    int64_t r0 = 0, r1 = 0;
+    if constexpr (STAGED) {
+      tile_stage(e.off, e.n, t0, t1, T);
+    } else {
+      tile_rows(e.off, e.n, t0, t1, T);
+      r0 = T[0];
+      r1 = T[1];
+    }
     for (int64_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
-      const int64_t u = row_search(e.off, r0, r1 + 1, j);
+      int64_t u;
+      if constexpr (STAGED) u = tile_row(e.off, T, t0, j);
+      else u = row_search(e.off, r0, r1 + 1, j);
       const int64_t b = e.off[u];
       const uint32_t k = (uint32_t)(j - b), su = e.ustart[u];
       if (k >= su)
@@ -343,7 +355,9 @@ __global__ void k_low_words(const uint64_t* __restrict__ items, int64_t m, uint3
 
 static void launch_emit_entries(const EmitArgs& e, int64_t nnz, hipStream_t s) {
   const int64_t tiles = (nnz + ETILE - 1) / ETILE;
-  k_emit_entries<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, 65536)), 256, 0, s>>>(e, nnz);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(tiles, 65536));
+  if (e.lower) k_emit_entries<true><<<grid, 256, 0, s>>>(e, nnz);
+  else k_emit_entries<false><<<grid, 256, 0, s>>>(e, nnz);
 }
 
 // ------------------------------------------------------------ the census
