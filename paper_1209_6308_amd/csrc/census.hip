@@ -1674,7 +1674,7 @@ int census_device(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
   }
   Events ev;
   if (o.timing) HIPCHK(ev.init());
-  Scratch scratch = arena ? Scratch(s, arena, arena_bytes) : Scratch(s, allocated_before);
+  Scratch scratch = arena ? Scratch(s, arena, arena_bytes) : Scratch(s, allocated_before, true);
   uint32_t* err = nullptr;
   // NC census counters, 2 queue counters, hub tasks, long rows, grouped-task claims
   unsigned long long* acc = nullptr;

@@ -439,7 +439,7 @@ int csr_from_arcs(int64_t n, int64_t narcs, const int32_t* src, const int32_t* d
     HIPCHK(hipStreamSynchronize(s));
     return done(0);
   }
-  Scratch scratch(s);
+  Scratch scratch(s, 0, true);
   const int rb = n > 1 ? 64 - __builtin_clzll((unsigned long long)(n - 1)) : 1;  // ids below 2^rb
   const int64_t N = 2 * narcs;
   uint64_t *ka = nullptr, *kb = nullptr;

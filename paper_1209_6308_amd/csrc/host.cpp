@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 
@@ -23,6 +24,97 @@ bool take_injected_fault() {
   while (k > 0)
     if (g_inject.compare_exchange_weak(k, k - 1)) return true;
   return false;
+}
+
+// Held device blocks (see held_take): per device, free blocks by size. The
+// table is never destroyed, so that nothing calls into HIP during static
+// destruction at process exit (the blocks die with the process).
+namespace {
+struct HeldBlocks {
+  std::mutex mu;
+  std::multimap<size_t, void*> free[64];
+  size_t bytes[64] = {};
+};
+HeldBlocks& held_blocks() {
+  static HeldBlocks* h = new HeldBlocks;
+  return *h;
+}
+// requests of 1 MiB and more are rounded up to whole MiB, smaller ones to 256 B
+size_t block_size(size_t b) {
+  const size_t g = b >= ((size_t)1 << 20) ? ((size_t)1 << 20) : 256;
+  return (b + g - 1) / g * g;
+}
+size_t release_device(int dev) {
+  HeldBlocks& h = held_blocks();
+  std::multimap<size_t, void*> out;
+  {
+    std::lock_guard<std::mutex> lk(h.mu);
+    out.swap(h.free[dev]);
+    h.bytes[dev] = 0;
+  }
+  size_t freed = 0;
+  for (const auto& b : out) {
+    (void)hipFree(b.second);
+    freed += b.first;
+  }
+  return freed;
+}
+}  // namespace
+
+hipError_t held_take(void** p, size_t bytes, size_t* got) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  HeldBlocks& h = held_blocks();
+  const size_t want = block_size(bytes);
+  {
+    std::lock_guard<std::mutex> lk(h.mu);
+    auto& m = h.free[dev];
+    auto it = m.lower_bound(want);
+    if (it != m.end() && it->first / 2 <= want) {
+      *p = it->second;
+      *got = it->first;
+      h.bytes[dev] -= it->first;
+      m.erase(it);
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, want);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    release_device(dev);
+    e = hipMalloc(p, want);
+  }
+  if (e == hipSuccess) *got = want;
+  return e;
+}
+
+void held_give(void* p, size_t bytes, int dev) {
+  if (dev >= 0 && dev < 64) {
+    HeldBlocks& h = held_blocks();
+    std::lock_guard<std::mutex> lk(h.mu);
+    if (h.bytes[dev] + bytes <= HELD_LIMIT) {
+      h.free[dev].emplace(bytes, p);
+      h.bytes[dev] += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
+size_t held_release_all() {
+  size_t freed = 0;
+  for (int d = 0; d < 64; ++d) freed += release_device(d);
+  return freed;
+}
+
+size_t held_bytes() {
+  HeldBlocks& h = held_blocks();
+  std::lock_guard<std::mutex> lk(h.mu);
+  size_t t = 0;
+  for (int d = 0; d < 64; ++d) t += h.bytes[d];
+  return t;
 }
 
 void set_error(const std::string& msg) { g_err = msg; }
@@ -158,6 +250,13 @@ int triad_version(void) { return TRIAD_ABI_VERSION; }
 int triad_set_memory_cap(int64_t bytes) {
   if (bytes < 0) return fail(TRIAD_EINVAL, "memory cap must be >= 0");
   g_mem_cap.store(bytes);
+  return TRIAD_OK;
+}
+
+int64_t triad_held_memory(void) { return (int64_t)held_bytes(); }
+
+int triad_release_memory(void) {
+  (void)held_release_all();
   return TRIAD_OK;
 }
 

@@ -82,21 +82,57 @@ inline bool within_cap(size_t total) {
 // raise ERR_DEVICE after its census kernel; set by triad_test_inject_device_error.
 bool take_injected_fault();
 
+// Device blocks the library keeps between calls, per device. A call that
+// drains its stream before it returns can take its scratch from here and give
+// it back on return, so that repeated calls of one shape allocate and free
+// nothing (freeing gigabytes costs milliseconds of host time per call).
+// held_take hands out a held block of at least `bytes` and at most twice that
+// (sizes rounded up to 256 B, or to whole MiB from 1 MiB on; its size in
+// *got), else allocates one (freeing every held block of the
+// device and retrying once if the device is out of memory); held_give keeps a
+// block unless the device's held bytes would pass HELD_LIMIT, then frees it.
+constexpr size_t HELD_LIMIT = (size_t)64 << 30;
+hipError_t held_take(void** p, size_t bytes, size_t* got);
+void held_give(void* p, size_t bytes, int device);
+size_t held_release_all();  // frees every held block; returns the bytes freed
+size_t held_bytes();        // bytes held, all devices
+
 // Scratch memory of one call. By default stream-ordered allocations, released
 // (in stream order) on destruction; `total` counts what the call has
 // allocated (starting from what it allocated before this object existed) and
-// a request that would take it past the memory cap fails. Given an arena (a
-// caller-owned device range), it hands out 256-byte aligned pieces of it
-// instead and allocates nothing; a request past the arena's end fails.
+// a request that would take it past the memory cap fails. Constructed with
+// held = true (for calls that drain their stream before returning), the blocks
+// come from the held blocks above and go back to them on destruction, after
+// the stream has drained (every use of them is on that stream). Given an
+// arena (a caller-owned device range), it hands out 256-byte aligned pieces of
+// it instead and allocates nothing; a request past the arena's end fails.
 struct Scratch {
   hipStream_t s;
   std::vector<void*> ptrs;
+  struct Block {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Block> blocks;  // held = true
+  bool held = false;
+  int device = -1;
   char* arena = nullptr;
   size_t cap = 0, used = 0, total = 0;
-  explicit Scratch(hipStream_t st, size_t allocated_before = 0) : s(st), total(allocated_before) {}
+  explicit Scratch(hipStream_t st, size_t allocated_before = 0, bool keep = false)
+      : s(st), held(keep), total(allocated_before) {
+    if (held && hipGetDevice(&device) != hipSuccess) held = false;
+  }
   Scratch(hipStream_t st, void* base, size_t bytes) : s(st), arena(static_cast<char*>(base)), cap(bytes) {}
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
   ~Scratch() {
     for (void* p : ptrs) (void)hipFreeAsync(p, s);
+    if (blocks.empty()) return;
+    if (hipStreamSynchronize(s) == hipSuccess) {
+      for (const Block& b : blocks) held_give(b.p, b.bytes, device);
+    } else {
+      for (const Block& b : blocks) (void)hipFree(b.p);
+    }
   }
   template <class T>
   hipError_t get(T** p, int64_t count) {
@@ -109,6 +145,15 @@ struct Scratch {
       return hipSuccess;
     }
     if (!within_cap(total + bytes)) return hipErrorOutOfMemory;
+    if (held) {
+      size_t got = 0;
+      hipError_t e = held_take((void**)p, bytes, &got);
+      if (e == hipSuccess) {
+        blocks.push_back({(void*)*p, got});
+        total += bytes;
+      }
+      return e;
+    }
     hipError_t e = hipMallocAsync((void**)p, bytes, s);
     if (e == hipSuccess) {
       ptrs.push_back(*p);

@@ -455,7 +455,7 @@ int census_update(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
     return fail(TRIAD_EINVAL, "NULL pointer argument");
   const bool new_csr = noff != nullptr;
   if (new_csr && (!nnz_new || !nnbr || !nflg)) return fail(TRIAD_EINVAL, "NULL pointer for the new CSR");
-  Scratch scratch(s);
+  Scratch scratch(s, 0, true);
   const int rb = std::max(1, 64 - __builtin_clzll((unsigned long long)std::max<int64_t>(n, 1)));
   uint32_t* err = nullptr;
   unsigned long long* delta = nullptr;

@@ -39,7 +39,7 @@ EXPORTS = [
     "triad_batch_plan_destroy", "triad_census_batch", "triad_batch_autotune",
     "triad_csr_from_arcs", "triad_census_update", "triad_significance_profile", "triad_task_features", "triad_mlp_forward", "triad_mlp_loss_grad", "triad_mlp_adam",
     "triad_mlp_train", "triad_last_error", "triad_version", "triad_set_memory_cap",
-    "triad_test_inject_device_error",
+    "triad_test_inject_device_error", "triad_held_memory", "triad_release_memory",
 ]
 
 
@@ -106,6 +106,7 @@ def lib():
             "triad_version": [],
             "triad_set_memory_cap": [i64],
             "triad_test_inject_device_error": [i32],
+            "triad_release_memory": [],
         }
         for name, args in sigs.items():
             if hasattr(L, name):
@@ -113,6 +114,9 @@ def lib():
                 fn.argtypes = args
                 fn.restype = ctypes.c_int
         L.triad_last_error.restype = ctypes.c_char_p
+        if hasattr(L, "triad_held_memory"):
+            L.triad_held_memory.argtypes = []
+            L.triad_held_memory.restype = ctypes.c_int64
         if hasattr(L, "triad_batch_plan_destroy"):
             L.triad_batch_plan_destroy.restype = None
         _LIB = L
@@ -174,6 +178,16 @@ def _result(out, hi):
 def set_memory_cap(nbytes):
     """Cap the device memory any one later call may allocate (0 = no cap)."""
     return _check(lib().triad_set_memory_cap(int(nbytes)))
+
+
+def held_memory():
+    """Bytes of device scratch the library holds between calls (all devices)."""
+    return int(lib().triad_held_memory())
+
+
+def release_memory():
+    """Free every device block the library holds between calls."""
+    return _check(lib().triad_release_memory())
 
 
 def inject_device_error(count):

@@ -104,6 +104,8 @@ def test_failure_controls_on_the_host():
     assert L.triad_set_memory_cap(1 << 20) == 0 and L.triad_set_memory_cap(0) == 0
     assert L.triad_test_inject_device_error(-2) == triad.EINVAL
     assert L.triad_test_inject_device_error(5) == 0 and L.triad_test_inject_device_error(0) == 0
+    # nothing is held before any device call; releasing nothing succeeds
+    assert triad.held_memory() == 0 and L.triad_release_memory() == 0
     # a cap does not change host-side validation
     n, off, nb, fl = _valid()
     triad.set_memory_cap(1)

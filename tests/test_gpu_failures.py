@@ -225,3 +225,35 @@ def test_batch_error_writes_nothing(torch):
     torch.cuda.synchronize()
     assert st == triad.ERANGE
     assert _untouched(out.cpu().numpy())
+
+
+def test_held_memory_is_reused_and_released(torch):
+    """Scratch blocks stay with the library between calls: a second call of the
+    same shape takes them again (the held total is unchanged after it), the
+    counts stay the oracle's, and releasing frees every held block."""
+    g = graphs.rmat(12, 8, seed=9, recip_p=0.15)
+    d = triad.to_device(g)
+    want = oracle.census(g)
+    triad.release_memory()
+    assert triad.held_memory() == 0
+    fn = triad.lib().triad_census_device
+    st, dw, hw = _raw(torch, fn, g, d, 17)
+    assert st == 0 and _counts(hw) == want
+    held = triad.held_memory()
+    assert held > 8 * g.nnz // 2  # at least the task list
+    for _ in range(2):
+        st, dw, hw = _raw(torch, fn, g, d, 17)
+        assert st == 0 and _counts(hw) == want and _counts(dw) == want
+        assert triad.held_memory() == held
+    # a failing call (device fault flagged) gives its blocks back as well
+    triad.inject_device_error(1)
+    st, dw, hw = _raw(torch, fn, g, d, 17)
+    assert st == triad.EDEVICE and _untouched(dw, hw)
+    assert triad.held_memory() == held
+    # the labelled census takes and gives back blocks as well
+    st, dw, hw = _raw(torch, triad.lib().triad_labelled_census_device, g, d, 65)
+    assert st == 0
+    assert triad.release_memory() == 0 and triad.held_memory() == 0
+    st, dw, hw = _raw(torch, fn, g, d, 17)
+    assert st == 0 and _counts(hw) == want
+    triad.release_memory()
