@@ -9,10 +9,13 @@
 //               Sec. 6 / Fig. 7, built once on the device)
 //   scan        exclusive prefix of tasks(u): the collapsed (u,v) task space
 //               of Fig. 5 steps 2 and 2.1
-//   k_emit_entries  task list in CSR order, one thread per entry, with each
-//               task's count of N(v) ids below u; tasks whose merge length
-//               d(u)+d(v) exceeds the hub threshold are flagged, and k_hub_list
-//               lists them
+//   k_emit_entries  task list in CSR order, one thread per entry; tasks whose
+//               merge length d(u)+d(v) exceeds the hub threshold are flagged.
+//               The entries below their row's id are listed as (id, index)
+//               pairs, which a stable radix sort by id puts in task order:
+//               their indices are the tasks' counts of N(v) ids below u
+//               (k_low_words; the no-allocation census searches u in N(v)
+//               per task instead). k_hub_list lists the flagged tasks.
 //   k_census    persistent wavefronts: hub chunks first, then tasks; each
 //               item merges a range of N(u) with a range of N(v)
 //   k_finalize  the common-neighbour part of 012 and 102 from the triangle
@@ -221,7 +224,9 @@ struct EmitArgs {
   const int64_t* tpre;
   uint64_t* tasks;
   uint32_t* tskip;        // per task: entries of N(v) below u
-  int32_t count_below;    // 0: write 0 to tskip (the merge then takes all of N(v))
+  // 1: tskip by a search of u in N(v); 0: no search, tskip gets 0 (the merge
+  // then takes all of N(v)), or nothing when `lower` is given (its sort does)
+  int32_t count_below;
   int64_t hub_threshold;  // < 0: no hub tasks
   const uint32_t* err;
   // optional: every entry below its row's own id, as (id << 32 | index in the
@@ -309,8 +314,10 @@ __global__ void __launch_bounds__(256) k_hub_list(const uint64_t* __restrict__ t
 
 // Task list from the CSR entries, one thread per entry: entry j of row u with
 // an id above u is task tpre[u] + (j - off[u] - ustart[u]) (CSR order), with
-// its count of N(v) ids below u and its hub flag (emit_task). Every task is
-// as cheap as the next, whatever the lengths of the rows.
+// its hub flag and, searched or left to the sort of the lower entries, its
+// count of N(v) ids below u (emit_task); an entry below u goes to the lower
+// entry list when there is one. Every task is as cheap as the next, whatever
+// the lengths of the rows.
 // STAGED: the tile's row starts come from LDS (the sort path, whose entries do
 // no global search of their own).
 template <bool STAGED>
