@@ -360,26 +360,121 @@ __global__ void k_new_offsets(int64_t n, int rb, const int64_t* __restrict__ off
 
 // Old entries to their new places: rows without changes shift as a whole;
 // in a changed row an entry moves by the insertions and deletions before it,
-// takes its new flag, or is dropped.
+// takes its new flag, or is dropped. The shift of an unchanged row, noff[x] -
+// off[x], changes only past a changed row, so a tile of ETILE entries whose
+// rows hold at most COPY_MAXCHG changed rows (the usual case) lists those rows
+// with their entry ranges, their ranges of change entries and the shift of
+// each run of unchanged rows between them: an entry finds its run by comparing
+// its index with the few range ends, and an entry of a changed row searches
+// only that row's change entries. Other tiles find each entry's row by a
+// search of LDS-staged row starts, and its row's change entries by a search of
+// all of them.
+constexpr int COPY_MAXCHG = 8;
+struct CopyTile {
+  TileRows T;                        // r[0], r[1]: rows of the tile's first and last entry
+  int64_t crow[COPY_MAXCHG];         // the tile's changed rows, ascending
+  int64_t cbeg[COPY_MAXCHG], cend[COPY_MAXCHG];  // their entry ranges
+  int64_t cex[COPY_MAXCHG], cexe[COPY_MAXCHG];   // their change entries E[cex, cexe)
+  int64_t sdelta[COPY_MAXCHG + 1];   // shift of the unchanged rows before changed row s
+  int32_t nchg;                      // changed rows; -1: too many (per-entry row search)
+};
+
 __global__ void __launch_bounds__(UT) k_copy_old(int64_t n, int64_t nnz, int rb, const int64_t* __restrict__ off,
                                                  const int32_t* __restrict__ nbr, const uint8_t* __restrict__ flg,
                                                  const uint64_t* __restrict__ E, int64_t nE,
                                                  const uint32_t* __restrict__ I, const uint32_t* __restrict__ D,
                                                  const uint32_t* __restrict__ mark, const int64_t* __restrict__ noff,
                                                  int64_t nn, int32_t* __restrict__ nnbr, uint8_t* __restrict__ nfl) {
-  __shared__ TileRows T;
+  __shared__ CopyTile C;
   for (int64_t t0 = (int64_t)blockIdx.x * ETILE; t0 < nnz; t0 += (int64_t)gridDim.x * ETILE) {
     const int64_t t1 = min(t0 + (int64_t)ETILE, nnz);
-    tile_stage(off, n, t0, t1, T);
+    __syncthreads();
+    if (threadIdx.x < 2) C.T.r[threadIdx.x] = row_search(off, 0, n, threadIdx.x == 0 ? t0 : t1 - 1);
+    __syncthreads();
+    const int64_t r0 = C.T.r[0], r1 = C.T.r[1];
+    // the changed rows among r0..r1 in ascending order, from the row marks:
+    // one mark word (32 rows) per lane of the first wavefront
+    if (threadIdx.x < 64) {
+      const int lane = (int)threadIdx.x;
+      const int64_t w0 = r0 >> 5, w1 = r1 >> 5;
+      int32_t total = -1;
+      if (w1 - w0 < 64) {
+        const int64_t w = w0 + lane;
+        uint32_t m = 0;
+        if (w <= w1) {
+          m = mark[w];
+          if (w == w0) m &= ~0u << (r0 & 31);
+          if (w == w1 && (r1 & 31) != 31) m &= (1u << ((r1 & 31) + 1)) - 1u;
+        }
+        const uint32_t c = (uint32_t)__popc(m);
+        uint32_t pre = c;  // inclusive prefix over the lanes
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t v = __shfl_up(pre, o, 64);
+          if (lane >= o) pre += v;
+        }
+        const uint32_t all = __shfl(pre, 63, 64);
+        if (all <= (uint32_t)COPY_MAXCHG) {
+          uint32_t q = pre - c;
+          while (m) {
+            C.crow[q++] = w * 32 + __builtin_ctz(m);
+            m &= m - 1u;
+          }
+          total = (int32_t)all;
+        }
+      }
+      if (lane == 0) C.nchg = total;
+    }
+    __syncthreads();
+    const int32_t nchg = C.nchg;
+    if (nchg >= 0) {
+      const int q = (int)threadIdx.x;
+      if (q <= nchg) {
+        const int64_t xs = q == 0 ? r0 : C.crow[q - 1] + 1;  // <= r1 + 1 <= n
+        C.sdelta[q] = noff[xs] - off[xs];
+        if (q < nchg) {
+          const int64_t c = C.crow[q];
+          C.cbeg[q] = off[c];
+          C.cend[q] = off[c + 1];
+          const int64_t ex = lower_key(E, 0, nE, (uint64_t)c << (rb + 4));
+          C.cex[q] = ex;
+          C.cexe[q] = lower_key(E, ex, nE, (uint64_t)(c + 1) << (rb + 4));
+        }
+      }
+    } else {
+      const int64_t nr = r1 - r0 + 1;
+      if (nr <= TILE_ROWS)
+        for (int64_t x = threadIdx.x; x < nr; x += blockDim.x) {
+          const int64_t d = off[r0 + x] - t0;
+          C.T.rel[x] = (uint16_t)(d > 0 ? d : 0);
+        }
+    }
+    __syncthreads();
     for (int64_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
-      const int64_t x = tile_row(off, T, t0, j);
       const int32_t y = nbr[j];
       uint32_t f = entry_flag(flg, j);
-      int64_t pos = noff[x] + (j - off[x]);
-      if ((mark[x >> 5] >> (x & 31)) & 1u) {
-        const int64_t ex = lower_key(E, 0, nE, (uint64_t)x << (rb + 4));
+      int64_t x, pos, ex = 0, exe = nE;
+      bool changed;
+      if (nchg >= 0) {
+        int sidx = 0;  // changed rows whose entries all lie before j
+        for (int q = 0; q < nchg; ++q) sidx += C.cend[q] <= j ? 1 : 0;
+        changed = sidx < nchg && j >= C.cbeg[sidx];
+        x = 0;
+        pos = j + C.sdelta[sidx];
+        if (changed) {
+          x = C.crow[sidx];
+          pos = noff[x] + (j - C.cbeg[sidx]);
+          ex = C.cex[sidx];
+          exe = C.cexe[sidx];
+        }
+      } else {
+        x = tile_row(off, C.T, t0, j);
+        changed = (mark[x >> 5] >> (x & 31)) & 1u;
+        pos = noff[x] + (j - off[x]);
+        if (changed) ex = lower_key(E, 0, nE, (uint64_t)x << (rb + 4));
+      }
+      if (changed) {
         const uint64_t k = (((uint64_t)x << rb) | (uint64_t)y) << 4;
-        const int64_t e = lower_key(E, ex, nE, k);
+        const int64_t e = lower_key(E, ex, exe, k);
         pos += ((int64_t)I[e] - (int64_t)I[ex]) - ((int64_t)D[e] - (int64_t)D[ex]);
         if (e < nE && (E[e] >> 4) == (k >> 4)) {
           f = (uint32_t)E[e] & 3u;
