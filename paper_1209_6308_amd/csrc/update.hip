@@ -229,6 +229,17 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
       int64_t i = lo, k = d0 - lo;
       // an id shared by A[i-1] and B[k] was taken with A[i-1] by a lane before
       if (i > 0 && k < lb && A[i - 1] == B[k]) ++k;
+      if (i + k >= d1) continue;
+      // The lane's ids ascend, and so do the change entries of a and of b: one
+      // search each for the first change at or after the lane's first id, then
+      // cursors that only move forward. (A change list holding only the pair
+      // {a, b} itself has no entry for any w walked here.)
+      const int32_t wfirst = min(i < la ? A[i] : INT32_MAX, k < lb ? B[k] : INT32_MAX);
+      int64_t pa = da1, pb = db1;
+      if (da1 - da0 > 1) pa = lower_key(g.E, da0, da1, (((uint64_t)a << g.rb) | (uint64_t)wfirst) << 4);
+      if (db1 - db0 > 1) pb = lower_key(g.E, db0, db1, (((uint64_t)b << g.rb) | (uint64_t)wfirst) << 4);
+      int64_t ida = pa < da1 ? (int64_t)((g.E[pa] >> 4) & cmask) : INT64_MAX;
+      int64_t idb = pb < db1 ? (int64_t)((g.E[pb] >> 4) & cmask) : INT64_MAX;
       while (i + k < d1) {
         const int32_t x = i < la ? A[i] : INT32_MAX, y = k < lb ? B[k] : INT32_MAX;
         const bool inA = x <= y, inB = y <= x;
@@ -236,18 +247,23 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
         const uint32_t fa = inA ? entry_flag(g.flg, oa + i) : 0u, fb = inB ? entry_flag(g.flg, ob + k) : 0u;
         i += inA;
         k += inB;
+        while (ida < w) {
+          ++pa;
+          ida = pa < da1 ? (int64_t)((g.E[pa] >> 4) & cmask) : INT64_MAX;
+        }
+        while (idb < w) {
+          ++pb;
+          idb = pb < db1 ? (int64_t)((g.E[pb] >> 4) & cmask) : INT64_MAX;
+        }
         if (w == a || w == b) continue;
         uint32_t g1a = fa;
         bool cha = false;
-        // (a change list holding only the pair {a, b} itself has no entry for w)
-        const int64_t pa = da1 - da0 > 1 ? find_change(g, da0, da1, a, w) : -1;
-        if (pa >= 0) {
+        if (ida == w) {
           if (!inA) continue;  // a pair with a that changes: the pass over the changes of a takes w
           cha = true;
           g1a = (uint32_t)(g.E[pa] & 3u);
         }
-        const int64_t pb = db1 - db0 > 1 ? find_change(g, db0, db1, b, w) : -1;
-        const bool chb = pb >= 0;
+        const bool chb = idb == w;
         const uint32_t g1b = chb ? (uint32_t)(g.E[pb] & 3u) : fb;
         ++ucount;
         triad_move(g, h, lane, pk, a, b, w, f0, f1, fa, g1a, cha, fb, g1b, chb);
