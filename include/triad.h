@@ -137,7 +137,8 @@ int triad_census_ex(int64_t n, const int64_t *csr_offsets, const int32_t *csr_nb
  * csr_offsets[n]. Results go to d_out (device, 17 x uint64: the 16 counts,
  * then the high word of 003) and, if h_out is not NULL, to h_out (host, 17 x
  * uint64). The call waits for its own work on the stream before returning the
- * status. Scratch memory is taken from the stream-ordered allocator. */
+ * status. Scratch memory comes from the library's held blocks (see
+ * triad_held_memory), allocated on first use. */
 int triad_census_device(int64_t n, int64_t nnz, const int64_t *csr_offsets, const int32_t *csr_nbrs,
                         const uint8_t *dir_flags, const triad_opts *opts, void *hip_stream, uint64_t *d_out,
                         uint64_t *h_out);
@@ -227,8 +228,8 @@ int triad_batch_autotune(int32_t G, int64_t nv, int64_t nnz, const int64_t *d_vb
  * construction measured with HIP events on the stream. Limits: n < 2^30,
  * narcs < 2^31. Errors: TRIAD_EINVAL (sizes, NULL pointers), TRIAD_ERANGE (an
  * endpoint outside [0, n); no output is written), TRIAD_ENOMEM. Scratch comes
- * from the stream-ordered allocator, about 35 bytes per arc. The call waits
- * for its work on hip_stream before returning. */
+ * from the library's held blocks (see triad_held_memory), about 35 bytes per
+ * arc. The call waits for its work on hip_stream before returning. */
 int triad_csr_from_arcs(int64_t n, int64_t narcs, const int32_t *d_src, const int32_t *d_dst, void *hip_stream,
                         int64_t *d_offsets, int32_t *d_nbrs, uint8_t *d_flags, int64_t *nnz_out,
                         float *device_ms);
@@ -253,7 +254,8 @@ int triad_csr_from_arcs(int64_t n, int64_t narcs, const int32_t *d_src, const in
  * TRIAD_ERANGE (an endpoint outside [0, n) or d_insert[i] > 1),
  * TRIAD_ESELFLOOP (an update of a self-loop), TRIAD_ENOMEM; nothing is written
  * on error. Returns TRIAD_OK_003_WRAPPED when the new 003 is >= 2^64. The
- * call waits for its work on hip_stream before returning. */
+ * call waits for its work on hip_stream before returning; its scratch comes
+ * from the library's held blocks (see triad_held_memory). */
 int triad_census_update(int64_t n, int64_t nnz, const int64_t *d_offsets, const int32_t *d_nbrs,
                         const uint8_t *d_flags, int64_t nupd, const int32_t *d_src, const int32_t *d_dst,
                         const uint8_t *d_insert, const uint64_t census_in[17], uint64_t census_out[17],
