@@ -218,8 +218,11 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
     const int32_t* const A = g.nbr + oa;
     const int32_t* const B = g.nbr + ob;
     const int64_t la = ea - oa, lb = eb - ob, D = la + lb;
-    for (int64_t r0 = 0; r0 < D; r0 += 64 * UPD_S) {
-      const int64_t d0 = min(D, r0 + (int64_t)lane * UPD_S), d1 = min(D, d0 + UPD_S);
+    // positions per lane and round: UPD_S, or fewer for a short merge so that
+    // it spreads over the whole wavefront
+    const int64_t S = D < 64 * UPD_S ? max((int64_t)1, (D + 63) >> 6) : (int64_t)UPD_S;
+    for (int64_t r0 = 0; r0 < D; r0 += 64 * S) {
+      const int64_t d0 = min(D, r0 + (int64_t)lane * S), d1 = min(D, d0 + S);
       // merge-path split of diagonal d0: A elements among the first d0 merged
       int64_t lo = d0 > lb ? d0 - lb : 0, hi = min(d0, la);
       while (lo < hi) {
