@@ -27,7 +27,8 @@
 //   k_run_heads     first operation of each pair
 //   k_pair_state    f0 from the CSR, f1 from the last operation on each arc
 //   k_changed_keys  two entries per changed pair (one per row), sorted
-//   k_upd_delta     one wavefront per changed pair: the class changes
+//   k_pair_chunks   merged positions of each changed pair cut into work items
+//   k_upd_delta     one wavefront per work item: the class changes
 //   k_row_marks, k_new_offsets, k_copy_old, k_insert_new, k_pack_bytes
 //                   the CSR after the batch
 #include <hip/hip_runtime.h>
@@ -151,7 +152,30 @@ struct DeltaArgs {
   int64_t nE;
   uint64_t lut[4];    // class of code c: nibble c & 15 of lut[c >> 4]
   unsigned long long* delta;  // [16], two's complement
+  // work items: item it is chunk it - ipre[q] of the pair of entry q (ipre:
+  // exclusive prefix of the chunk counts, ipre[nE] = the item count)
+  const uint32_t* ipre;
 };
+
+// Merged positions of N(a) and N(b) per work item: a longer pair is cut into
+// chunks of about UPD_CHUNK positions (at most maxch chunks, which keeps the
+// item count below 2^32) that different wavefronts walk, so that a pair on a
+// hub row does not hold one wavefront for the whole of its merge.
+constexpr int64_t UPD_CHUNK = 8192;
+
+// Chunk count of the pair of each change entry (0 for the entry in the upper
+// row: a pair is processed from its lower row).
+__global__ void k_pair_chunks(const uint64_t* __restrict__ E, int64_t nE, int rb, const int64_t* __restrict__ off,
+                              uint32_t maxch, uint32_t* __restrict__ nch) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t cmask = (1ull << rb) - 1;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nE; q += stride) {
+    const uint64_t ent = E[q];
+    const int64_t a = (int64_t)(ent >> (4 + rb)), b = (int64_t)((ent >> 4) & cmask);
+    const int64_t D = (off[a + 1] - off[a]) + (off[b + 1] - off[b]);
+    nch[q] = b < a ? 0u : (uint32_t)min((int64_t)maxch, max((int64_t)1, (D + UPD_CHUNK - 1) / UPD_CHUNK));
+  }
+}
 
 __device__ __forceinline__ uint32_t class_of(const DeltaArgs& g, uint32_t code) {
   const uint64_t w = code < 16 ? g.lut[0] : code < 32 ? g.lut[1] : code < 48 ? g.lut[2] : g.lut[3];
@@ -185,14 +209,15 @@ __device__ __forceinline__ void triad_move(const DeltaArgs& g, int32_t* h, int l
   }
 }
 
-// One wavefront per changed pair {a, b} (the entries of row a in E). The third
-// vertices are the union of four sorted lists: N(a), the changes of a, N(b),
-// the changes of b. N(a) and N(b) are walked together, merged in id order (a
-// merge path cut into 16 positions per lane and round, a common id consumed
-// once), so each vertex of either row comes with both old flags; a vertex
-// adjacent to b only whose pair with a changes is left to the pass over the
-// changes of a. The changes of a, then of b, follow, each vertex seen in an
-// earlier list skipped.
+// One wavefront per work item: a chunk of the merge of a changed pair {a, b}
+// (the pairs are the entries of row a in E with a < b). The third vertices are
+// the union of four sorted lists: N(a), the changes of a, N(b), the changes of
+// b. N(a) and N(b) are walked together, merged in id order (a merge path cut
+// into 16 positions per lane and round, a common id consumed once), so each
+// vertex of either row comes with both old flags; a vertex adjacent to b only
+// whose pair with a changes is left to the pass over the changes of a. The
+// pair's first item then takes the changes of a, then of b, each vertex seen
+// in an earlier list skipped.
 __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
   __shared__ int32_t hist[UT / 64][16][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -201,11 +226,18 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const uint64_t cmask = (1ull << g.rb) - 1;
   uint32_t steps = 0;
-  for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < g.nE; q += nw) {
+  const int64_t nit = g.ipre[g.nE];
+  for (int64_t it = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; it < nit; it += nw) {
+    // the item's pair: the last entry q with ipre[q] <= it (one with chunks)
+    int64_t q = 0;
+    for (int64_t hi = g.nE; hi - q > 1;) {
+      const int64_t mid = (q + hi) >> 1;
+      if ((int64_t)g.ipre[mid] <= it) q = mid; else hi = mid;
+    }
+    const int64_t chunk = it - (int64_t)g.ipre[q];
     const uint64_t ent = g.E[q];
     const int64_t a = (int64_t)(ent >> (4 + g.rb));
     const int32_t b = (int32_t)((ent >> 4) & cmask);
-    if (b < a) continue;  // the pair is processed from its lower row
     const uint32_t f0 = (ent >> 2) & 3u, f1 = ent & 3u;
     const uint64_t pk = ((uint64_t)a << g.rb) | (uint64_t)b;
     const int64_t oa = g.off[a], ea = g.off[a + 1], ob = g.off[b], eb = g.off[b + 1];
@@ -218,11 +250,15 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
     const int32_t* const A = g.nbr + oa;
     const int32_t* const B = g.nbr + ob;
     const int64_t la = ea - oa, lb = eb - ob, D = la + lb;
-    // positions per lane and round: UPD_S, or fewer for a short merge so that
-    // it spreads over the whole wavefront
-    const int64_t S = D < 64 * UPD_S ? max((int64_t)1, (D + 63) >> 6) : (int64_t)UPD_S;
-    for (int64_t r0 = 0; r0 < D; r0 += 64 * S) {
-      const int64_t d0 = min(D, r0 + (int64_t)lane * S), d1 = min(D, d0 + S);
+    // this item's merged positions [c0, c1) (the pair's nq chunks cover its
+    // merge); per lane and round UPD_S of them, or fewer for a short range so
+    // that it spreads over the wavefront
+    const int64_t nq = (int64_t)g.ipre[q + 1] - (int64_t)g.ipre[q];
+    const int64_t csz = (D + nq - 1) / nq;
+    const int64_t c0 = min(D, chunk * csz), c1 = min(D, c0 + csz);
+    const int64_t S = c1 - c0 < 64 * UPD_S ? max((int64_t)1, (c1 - c0 + 63) >> 6) : (int64_t)UPD_S;
+    for (int64_t r0 = c0; r0 < c1; r0 += 64 * S) {
+      const int64_t d0 = min(c1, r0 + (int64_t)lane * S), d1 = min(c1, d0 + S);
       // merge-path split of diagonal d0: A elements among the first d0 merged
       int64_t lo = d0 > lb ? d0 - lb : 0, hi = min(d0, la);
       while (lo < hi) {
@@ -272,8 +308,9 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
         triad_move(g, h, lane, pk, a, b, w, f0, f1, fa, g1a, cha, fb, g1b, chb);
       }
     }
-    // the changes of a (vertices not in N(a)), then of b (not in N(b), not seen before)
-    for (int phase = 1; phase < 4; phase += 2) {
+    // the changes of a (vertices not in N(a)), then of b (not in N(b), not
+    // seen before): the pair's first item only
+    for (int phase = 1; phase < 4 && chunk == 0; phase += 2) {
       const int64_t L0 = phase == 1 ? da0 : db0;
       const int64_t L1 = phase == 1 ? da1 : db1;
       for (int64_t j0 = L0; j0 < L1; j0 += 64) {
@@ -315,18 +352,20 @@ __global__ void __launch_bounds__(UT) k_upd_delta(DeltaArgs g) {
         triad_move(g, h, lane, pk, a, b, w, f0, f1, g0a, g1a, cha, g0b, g1b, chb);
       }
     }
-    // every other third vertex: only the pair {a, b} has arcs
+    // every other third vertex: only the pair {a, b} has arcs. Those are the
+    // n - 2 others less the vertices the pair's items met; each item takes
+    // its own count off (the first adds the n - 2).
     uint32_t u = ucount;
     for (int o = 32; o > 0; o >>= 1) u += __shfl_xor(u, o, 64);
     if (lane == 0) {
-      const int64_t rest = g.n - 2 - (int64_t)u;
+      const int64_t rest = (chunk == 0 ? g.n - 2 : 0) - (int64_t)u;
       const uint32_t oc = class_of(g, f0), nc = class_of(g, f1);
-      if (rest > 0 && oc != nc) {
+      if (rest != 0 && oc != nc) {
         atomicAdd(&g.delta[oc], (unsigned long long)(-rest));
         atomicAdd(&g.delta[nc], (unsigned long long)rest);
       }
     }
-    steps += (uint32_t)((ea - oa + eb - ob + da1 - da0 + db1 - db0) / 64 + 4);
+    steps += (uint32_t)((c1 - c0 + da1 - da0 + db1 - db0) / 64 + 4);
     if (steps > (1u << 29)) {
       __builtin_amdgcn_wave_barrier();
       for (int c = 0; c < 16; ++c) {
@@ -631,6 +670,13 @@ int census_update(int64_t n, int64_t nnz, const int64_t* off, const int32_t* nbr
       g.nE = 2 * K;
       for (int c = 0; c < 64; ++c) g.lut[c >> 4] |= (uint64_t)classify_code((unsigned)c) << (4 * (c & 15));
       g.delta = delta;
+      uint32_t *nch = nullptr, *ipre = nullptr;
+      ALLOC(nch, 2 * K);
+      ALLOC(ipre, 2 * K + 1);
+      const uint32_t maxch = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(4096, 0xFFFFFFFFll / (2 * K)));
+      k_pair_chunks<<<grid_of(2 * K, 256, 65536), 256, 0, s>>>(E, 2 * K, rb, off, maxch, nch);
+      if (int st = scan_u32(nch, 2 * K, ipre, ipre + 2 * K, scratch, s)) return st;
+      g.ipre = ipre;
       k_upd_delta<<<grid_of(2 * K * 64, UT, 8192), UT, 0, s>>>(g);
       HIPCHK(hipGetLastError());
     }
