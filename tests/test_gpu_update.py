@@ -86,6 +86,22 @@ def test_rmat_with_hubs(torch):
     _run_series(torch, 1 << 12, src, dst, [3000, 1, 500], 11)
 
 
+def test_long_pairs_and_sparse_rows(torch):
+    """Two hub rows (20,000 and 15,000 neighbours): their changed pairs merge
+    more than 8,192 positions and are cut into several work items; the CSR copy
+    meets tiles inside a hub row (one changed row), a tile holding the end of
+    one hub row and the start of the other, and tiles over thousands of short
+    or empty rows (the per-entry row search)."""
+    n = 120_000
+    rng = np.random.default_rng(21)
+    h0 = rng.choice(np.arange(2, 60_000), 20_000, replace=False)
+    h1 = rng.choice(np.arange(2, 60_000), 15_000, replace=False)
+    sp = np.arange(60_000, n, 97)
+    src = np.concatenate([np.zeros(h0.size), np.ones(h1.size), [0], sp[:-1]]).astype(np.int32)
+    dst = np.concatenate([h0, h1, [1], sp[1:]]).astype(np.int32)
+    _run_series(torch, n, src, dst, [50, 400, 3000], 5)
+
+
 def test_from_empty_and_to_empty(torch):
     n = 9
     arcs = [(0, 1), (1, 2), (2, 0), (3, 4), (4, 3), (5, 6), (6, 7), (7, 5), (8, 0)]
