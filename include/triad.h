@@ -329,12 +329,14 @@ int triad_set_memory_cap(int64_t bytes);
 
 /* Held device memory. The census entry points that allocate
  * (triad_census_device, triad_labelled_census_device), triad_csr_from_arcs
- * and triad_census_update wait for their stream before they return; their
- * scratch blocks are then kept by the library, per device, and reused by later
- * calls that need a block of at least the same size and at most twice it
- * (sizes rounded up to 256 B, and to whole MiB from 1 MiB on),
- * instead of being freed and allocated again (at R-MAT scale 24 a census takes
- * about 15 GB of scratch, whose release alone costs milliseconds). At most
+ * and triad_census_update wait for their stream before they return. When the
+ * stream belongs to the current device, their scratch blocks are then kept by
+ * the library, per device, and reused by later calls that need a block of at
+ * least the same size and at most twice it (sizes rounded up to 256 B, and to
+ * whole MiB from 1 MiB on), instead of being freed and allocated again (at
+ * R-MAT scale 24 a census takes about 15 GB of scratch, whose release alone
+ * costs milliseconds); a stream of another device gets stream-ordered
+ * allocations on that device, freed on return. At most
  * 64 GiB of free blocks are kept per device; an allocation that finds the
  * device out of memory frees that device's held blocks and tries again.
  * triad_held_memory: the bytes held now (free blocks, all devices).

@@ -120,7 +120,13 @@ struct Scratch {
   size_t cap = 0, used = 0, total = 0;
   explicit Scratch(hipStream_t st, size_t allocated_before = 0, bool keep = false)
       : s(st), held(keep), total(allocated_before) {
-    if (held && hipGetDevice(&device) != hipSuccess) held = false;
+    // held blocks live on the current device: a stream of another device
+    // takes stream-ordered allocations on its own device instead
+    hipDevice_t sd = -1;
+    if (held && (hipGetDevice(&device) != hipSuccess || hipStreamGetDevice(s, &sd) != hipSuccess || sd != device)) {
+      (void)hipGetLastError();
+      held = false;
+    }
   }
   Scratch(hipStream_t st, void* base, size_t bytes) : s(st), arena(static_cast<char*>(base)), cap(bytes) {}
   Scratch(const Scratch&) = delete;
