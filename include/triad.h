@@ -72,7 +72,9 @@ enum triad_status {
  * otherwise CSR order stays. */
 enum triad_schedule {
   TRIAD_SCHED_PLAIN = 0,     /* tasks in CSR order */
-  TRIAD_SCHED_HEURISTIC = 1, /* last batches costliest first by the sum of d(u)+d(v) */
+  TRIAD_SCHED_HEURISTIC = 1, /* last batches costliest first by the summed merge lengths
+                                of their tasks (ids of N(u) above u plus ids of N(v)
+                                from u on) */
   TRIAD_SCHED_LEARNED = 2    /* last batches costliest first by the learned cost model's
                                 predicted cycles, summed over the batch */
 };
